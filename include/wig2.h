@@ -1,0 +1,182 @@
+/*
+ * wig2.h -- C ABI of the MI355X (gfx950) two-body Wigner step library.
+ *
+ * The library advances the two-particle Wigner function f(x1, x2, p1, p2) of
+ * Liang & Xiong, arXiv:2511.11354 (the two-body truncated Wigner equation of
+ * Sec. 2.4, eq. two_body_truncated_Wigner) on a 4-D grid:
+ *
+ *   df/dt + (p1/m) df/dx1 + (p2/m) df/dx2
+ *        = Theta_{V_eff[n1]} f + Theta_{V_eff[n2]} f + Theta_{V12} f,
+ *
+ * V_eff = V_ext + lambda * V_H[n] + V_xc[n] - V_xc[n0] (Sec. 2.2-2.3).  The
+ * step splits the characteristic advection (cubic B-spline interpolation,
+ * Sec. 4.1) from the pseudo-differential operator Theta (Sec. 3):
+ *   - torus [x_min, x_max): pseudo-difference operators (Sec. 3.1,
+ *     eqs. Hartree_FSM and two_body_FSM), dp = hbar*pi/L;
+ *   - box [x_min, x_max] (non-periodic): natural-boundary spline and the
+ *     Chebyshev spectral-element single-body operator (Sec. 3.2.1,
+ *     eq. Chebyshev_PDO).
+ *
+ * Conventions for every entry point:
+ *   - Return 0 on success, a negative WIG2_E* code otherwise.  No C++
+ *     exception crosses the ABI.  wig2_last_error() holds a message for the
+ *     last failing call on a context until the next call on it.
+ *   - State layout: f[((i1*nx + i2)*nk + n1)*nk + n2] (n2 fastest), i.e. each
+ *     x-pair owns one contiguous nk x nk momentum plane.
+ *   - Host arrays are read or written only during the call.  Device pointers
+ *     ("_dev") are caller-owned hipMalloc (or torch) memory of the state's
+ *     element type and size; the library only reads/writes them on the
+ *     context's stream during the call.
+ *   - Calls on one context are ordered on its stream.  Use one context per
+ *     host thread.  wig2_get_state, wig2_observables and the *_host variants
+ *     synchronise the stream; the others are asynchronous.
+ */
+#ifndef WIG2_H
+#define WIG2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WIG2_OK 0
+#define WIG2_EINVAL (-1)   /* invalid argument or grid/parameter combination   */
+#define WIG2_ENOMEM (-2)   /* device or host allocation failed                 */
+#define WIG2_EDEVICE (-3)  /* HIP runtime error (message has the HIP string)   */
+#define WIG2_ESTATE (-4)   /* call out of order (step before state/potentials)  */
+#define WIG2_ENOTSUP (-5)  /* combination not supported by this build          */
+#define WIG2_ENUMERIC (-6) /* NaN or Inf met in the observables                */
+
+enum { WIG2_STRANG = 0, WIG2_LAWSON_PC = 1 };
+enum { WIG2_FP64 = 0, WIG2_FP32 = 1, WIG2_BF16X2 = 2 };
+
+typedef struct wig2_ctx wig2_ctx;
+
+/* Host callback: potential value at x (V_ext) or at separation r (V12).
+ * Called synchronously inside wig2_set_potentials only, never retained. */
+typedef double (*wig2_fn1)(double x, void* user);
+
+/* Grid (Sec. 3.1 torus / Sec. 3.2 box).
+ *  nx        points per x-dimension.  Torus: distinct points, dx = L/nx.
+ *            Box: nodes including both ends, dx = L/(nx-1).  nx >= 4.
+ *  nk        points per p-dimension.  nk >= 2.  The Theta kernels need nk a
+ *            multiple of 16 (other sizes: WIG2_ENOTSUP).
+ *  periodic  1: torus, p_n = (n - nk/2) hbar pi / L.
+ *            0: box; nk = sem_cells * N Chebyshev-Gauss nodes on
+ *               [-hbar k_max, hbar k_max].
+ *  sem_cells spectral-element cells per p-dimension (box only; nk % sem_cells == 0).
+ *  x_min, x_max  spatial extent, x_max > x_min.
+ *  k_max     box only: half-width of the p-box in wave-number units. */
+typedef struct {
+    int32_t nx, nk, periodic, sem_cells;
+    double x_min, x_max, k_max;
+} wig2_grid;
+
+/* Physical and numerical parameters.
+ *  hbar, mass, dt   > 0.
+ *  scheme           WIG2_STRANG: A(dt/2), Heun on Theta (potential frozen at
+ *                   the sub-step start), A(dt/2).
+ *                   WIG2_LAWSON_PC: the Lawson predictor-corrector of Sec. 4.1.
+ *  precision        WIG2_FP64; WIG2_FP32 (state, advection and Theta in FP32);
+ *                   WIG2_BF16X2 (FP32 state and advection, Theta on bf16
+ *                   matrix cores with hi+lo split operands, FP32 accumulate).
+ *                   Symbol tables and all reductions stay FP64.
+ *  meanfield_lambda weight of the Hartree term lambda * (V12 * n_j) on
+ *                   particle j (the (N-k)/(N-1) prefactor of Sec. 2.1; 0 for N=2).
+ *  xc               1: add the Hedin-Lundqvist potential (Sec. 2.2) in atomic
+ *                   units, evaluated at n_scale * n_j(x), minus its value at xc_n0.
+ *  Mean field (lambda != 0 or xc) is supported on the torus only. */
+typedef struct {
+    double hbar, mass, dt;
+    int32_t scheme, precision;
+    double meanfield_lambda;
+    int32_t xc;
+    double xc_n0, n_scale;
+} wig2_params;
+
+/* Scalar observables (Sec. 2.2, Appendix B).
+ *  mass = int f, energy = int f (p1^2/2m + p2^2/2m + V_ext(x1) + V_ext(x2)
+ *  + V12(x1-x2)), l2 = int f^2, entropy_vn = -sum lam ln lam of the trace-one
+ *  1-RDM occupations.  fallbacks counts surrogate blocks redone exactly. */
+typedef struct {
+    int64_t step;
+    double t, mass, energy, l2, entropy_vn;
+    int32_t fallbacks;
+} wig2_obs;
+
+/* Create a context on the current HIP device.  hip_stream: a hipStream_t to
+ * run on, or NULL for a stream owned by the context.  Allocates the state and
+ * work buffers (3 state-sized arrays) on the device.  *out owns them. */
+int wig2_create(const wig2_grid* grid, const wig2_params* params, void* hip_stream,
+                wig2_ctx** out);
+
+/* Sample the potentials and build the symbol tables (FP64, host) then upload.
+ * Torus: V_ext at y_j = x_min + j L/(2nk) for its symbol (Sec. 3.1.1),
+ * V12 at r_j = -L/2 + j L/(2nk) for its Fourier modes (Sec. 3.1.2, even V12
+ * assumed), both at the grid nodes / minimum-image separations for the
+ * energy and the Hartree term.  Box: V_ext at the nodes for the SEM operator
+ * (Sec. 3.2.1); v12 must be NULL (WIG2_ENOTSUP otherwise).
+ * v_ext or v12 NULL means zero. */
+int wig2_set_potentials(wig2_ctx* ctx, wig2_fn1 v_ext, wig2_fn1 v12, void* user);
+
+/* Upload / download the state as FP64 host arrays of nx*nx*nk*nk values
+ * (converted to the state's element type). */
+int wig2_set_state(wig2_ctx* ctx, const double* f_host);
+int wig2_get_state(wig2_ctx* ctx, double* f_host);
+
+/* Device-side state access for zero-copy interop: *f_dev receives the
+ * context-owned state buffer, *elem_bytes its element size (8 = FP64,
+ * 4 = FP32).  Valid until wig2_destroy. */
+int wig2_state_buffer(wig2_ctx* ctx, void** f_dev, int32_t* elem_bytes);
+/* Mark the state buffer as initialised after the caller wrote it. */
+int wig2_state_written(wig2_ctx* ctx);
+
+/* Advance nsteps steps of the configured scheme (asynchronous). */
+int wig2_step(wig2_ctx* ctx, int64_t nsteps);
+
+/* Observables of the current state (synchronises).  n1[nx], n12[nx*nx] (x1
+ * major), f1[nx*nk] (reduced Wigner function W_red(x1,p1)) may be NULL.
+ * Entropy from the 1-RDM of f1 on the even sub-lattice (Appendix B). */
+int wig2_observables(wig2_ctx* ctx, wig2_obs* obs, double* n1, double* n12, double* f1);
+
+/* Operator-level entry points (for verification and composition).
+ *  wig2_theta: out = Theta[in] with the current potentials (mean field, if
+ *    on, from the density of `in`).
+ *  wig2_advect: one spline sweep along x_dim (dim 1 or 2) by time s:
+ *    out(x, p) = in(x_dim - s p_dim / m, p).  in != out. */
+int wig2_theta(wig2_ctx* ctx, const void* in_dev, void* out_dev);
+int wig2_advect(wig2_ctx* ctx, int32_t dim, double s, const void* in_dev, void* out_dev);
+
+/* Per-kernel-class timing of wig2_step with HIP events on the context stream
+ * (a tracing aid; adds two event records per launch while enabled).
+ * wig2_profile_read synchronises, then fills ms[WIG2_PROF_N] (total
+ * milliseconds) and counts[WIG2_PROF_N] (launches) accumulated since the
+ * last reset; reset != 0 clears them.  Either array may be NULL. */
+enum {
+    WIG2_PROF_ADVECT_X1 = 0,
+    WIG2_PROF_ADVECT_X2 = 1,
+    WIG2_PROF_THETA_STAGE1 = 2, /* Theta[f]                                */
+    WIG2_PROF_THETA_STAGE2 = 3, /* u + tau/2 (v + Theta[u + tau v])        */
+    WIG2_PROF_MEANFIELD = 4,    /* density moments + mean-field symbols     */
+    WIG2_PROF_N = 5
+};
+int wig2_profile(wig2_ctx* ctx, int32_t enable);
+int wig2_profile_read(wig2_ctx* ctx, double* ms, int64_t* counts, int32_t reset);
+
+/* Largest single-body mode the Theta kernels visit: the symbol's support
+ * (modes below 1e-13 of the largest are dropped), nk-1 when dense or when the
+ * mean field is on.  >= 0 on success. */
+int wig2_band(const wig2_ctx* ctx);
+
+/* Grid nodes: x[nx], p[nk] and p-quadrature weights w[nk] (any may be NULL). */
+int wig2_nodes(const wig2_ctx* ctx, double* x, double* p, double* w);
+
+void wig2_destroy(wig2_ctx* ctx);
+const char* wig2_strerror(int code);
+const char* wig2_last_error(const wig2_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

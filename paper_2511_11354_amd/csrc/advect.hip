@@ -1,0 +1,314 @@
+// Cubic B-spline advection sweeps (Sec. 4.1) for gfx950.
+//
+// One lane owns one 1-D line along x_dim at fixed (other x, n1, n2).  Lanes of
+// a wavefront take consecutive n2, so every load/store of a wavefront is one
+// contiguous 64-element run (coalesced), whichever dimension is swept.
+//
+// Spline coefficients: periodic lines solve the circulant system
+// (eta_{i-1} + 4 eta_i + eta_{i+1})/6 = g_i exactly by the factorised
+// recursive filter 6/(z + 4 + 1/z) = -6 z1 / ((1 - z1/z)(1 - z1 z)),
+// z1 = sqrt(3) - 2, with the periodic initial values summed over the whole
+// period.  Box lines use the natural end conditions with zero ghost values
+// (A_nat of Sec. 4.1), which fix eta_0 = g_0, eta_{n-1} = g_{n-1} and leave a
+// (1,4,1) tridiagonal system for the interior (Thomas, multipliers from a
+// table).  The displacement c = s p / (m dx) is the same for the whole line,
+// so the evaluation at the feet x_i - c dx is a short FIR over the
+// coefficients with per-lane taps.
+#include "common.h"
+
+#include <cmath>
+
+namespace wig2 {
+namespace {
+
+constexpr int kThomasMax = 1024;
+
+template <typename T>
+__device__ inline void cubic_weights(T t, T& w0, T& w1, T& w2, T& w3)
+{
+    const T s = T(1) - t;
+    const T t2 = t * t, t3 = t2 * t;
+    w0 = s * s * s * T(1.0 / 6.0);
+    w1 = (T(3) * t3 - T(6) * t2 + T(4)) * T(1.0 / 6.0);
+    w2 = (T(-3) * t3 + T(3) * t2 + T(3) * t + T(1)) * T(1.0 / 6.0);
+    w3 = t3 * T(1.0 / 6.0);
+}
+
+struct LineMap {
+    long base, stride;
+    int nv;
+};
+
+__device__ inline LineMap line_map(long line, int nx, int nk, int dim)
+{
+    const long nk2 = (long)nk * nk;
+    const long o = line / nk2, rem = line - o * nk2;
+    LineMap m;
+    if (dim == 1) {  // line along i1 at fixed (i2 = o, n1, n2)
+        m.base = o * nk2 + rem;
+        m.stride = (long)nx * nk2;
+        m.nv = (int)(rem / nk);
+    } else {  // line along i2 at fixed (i1 = o, n1, n2)
+        m.base = o * nx * nk2 + rem;
+        m.stride = nk2;
+        m.nv = (int)(rem % nk);
+    }
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident line (NX compile-time): loads, solve and FIR unrolled.
+// Handles displacements |c| <= 1 cell (taps d in [-2, 2]).
+// ---------------------------------------------------------------------------
+template <typename T, int NX, bool PER>
+__global__ __launch_bounds__(64) void k_advect_reg(const T* __restrict__ in, T* __restrict__ out,
+                                                   int nk, int dim, long nlines, double cpp,
+                                                   const double* __restrict__ pn,
+                                                   const double* __restrict__ thomas)
+{
+    const long line = (long)blockIdx.x * 64 + threadIdx.x;
+    if (line >= nlines) return;
+    const LineMap lm = line_map(line, NX, nk, dim);
+    const double c = cpp * pn[lm.nv];  // displacement in cells
+
+    T v[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) v[i] = in[lm.base + (long)i * lm.stride];
+
+    T em1 = T(0), eN = T(0);  // box: eta_{-1}, eta_{NX}
+    T scale;
+    if constexpr (PER) {
+        const T z1 = T(-2.0 + 1.7320508075688772935274463415059);
+        // causal filter, periodic start value over the full period
+        T zk = T(1), s = T(0);
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+            s += zk * v[(NX - k) % NX];
+            zk *= z1;
+        }
+        const T inv = T(1) / (T(1) - zk);
+        v[0] = s * inv;
+#pragma unroll
+        for (int i = 1; i < NX; ++i) v[i] += z1 * v[i - 1];
+        // anti-causal filter, periodic start value
+        zk = T(1);
+        s = T(0);
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+            s += zk * v[(NX - 1 + k) % NX];
+            zk *= z1;
+        }
+        v[NX - 1] = s * inv;
+#pragma unroll
+        for (int i = NX - 2; i >= 0; --i) v[i] += z1 * v[i + 1];
+        scale = T(-6) * z1;  // eta = scale * v
+    } else {
+        // natural ends: eta_0 = g_0, eta_{N-1} = g_{N-1}; interior Thomas
+        const T e0 = v[0], eL = v[NX - 1];
+        T dprev = T(0);
+#pragma unroll
+        for (int i = 1; i <= NX - 2; ++i) {
+            T rhs = T(6) * v[i] - dprev;
+            if (i == 1) rhs -= e0;
+            if (i == NX - 2) rhs -= eL;
+            dprev = rhs * T(thomas[i]);
+            v[i] = dprev;
+        }
+#pragma unroll
+        for (int i = NX - 3; i >= 1; --i) v[i] -= T(thomas[i]) * v[i + 1];
+        em1 = T(2) * v[0] - v[1];
+        eN = T(2) * v[NX - 1] - v[NX - 2];
+        scale = T(1);
+    }
+
+    // taps: out_i = sum_d a_d eta_{i+d}, d in [-2, 2]; J = floor(-c), t = -c - J
+    const double mc = -c;
+    const double Jd = floor(mc);
+    const int J = (int)Jd;
+    T w0, w1, w2, w3;
+    cubic_weights(T(mc - Jd), w0, w1, w2, w3);
+    T a[5];
+#pragma unroll
+    for (int d = -2; d <= 2; ++d) {
+        const int k = d - J + 1;
+        T ad = (k == 0) ? w0 : (k == 1) ? w1 : (k == 2) ? w2 : (k == 3) ? w3 : T(0);
+        a[d + 2] = ad * scale;
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+        T acc = T(0);
+#pragma unroll
+        for (int d = -2; d <= 2; ++d) {
+            T e;
+            if constexpr (PER) {
+                e = v[(i + d + NX) % NX];
+            } else {
+                const int j = i + d;
+                e = (j >= 0 && j < NX) ? v[j < 0 ? 0 : (j >= NX ? NX - 1 : j)]
+                                       : (j == -1 ? em1 : (j == NX ? eN : T(0)));
+            }
+            acc += a[d + 2] * e;
+        }
+        if constexpr (!PER) {
+            const double u = (double)i - c;
+            if (u < 0.0 || u > (double)(NX - 1)) acc = T(0);
+        }
+        out[lm.base + (long)i * lm.stride] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// General line (any nx, any displacement): the coefficients go through a
+// state-sized scratch array laid out like the state (coalesced).
+// ---------------------------------------------------------------------------
+template <typename T, bool PER>
+__global__ __launch_bounds__(64) void k_advect_any(const T* __restrict__ in, T* __restrict__ out,
+                                                   T* __restrict__ ws, int nx, int nk, int dim,
+                                                   long nlines, double cpp,
+                                                   const double* __restrict__ pn,
+                                                   const double* __restrict__ thomas)
+{
+    const long line = (long)blockIdx.x * 64 + threadIdx.x;
+    if (line >= nlines) return;
+    const LineMap lm = line_map(line, nx, nk, dim);
+    const double c = cpp * pn[lm.nv];
+    auto G = [&](int i) { return in[lm.base + (long)i * lm.stride]; };
+    auto E = [&](int i) -> T& { return ws[lm.base + (long)i * lm.stride]; };
+    T em1 = T(0), eN = T(0), scale;
+    if constexpr (PER) {
+        const T z1 = T(-2.0 + 1.7320508075688772935274463415059);
+        T zk = T(1), s = T(0);
+        for (int k = 0; k < nx; ++k) {
+            s += zk * G((nx - k) % nx);
+            zk *= z1;
+        }
+        const T inv = T(1) / (T(1) - zk);
+        T prev = s * inv;
+        E(0) = prev;
+        for (int i = 1; i < nx; ++i) {
+            prev = G(i) + z1 * prev;
+            E(i) = prev;
+        }
+        zk = T(1);
+        s = T(0);
+        for (int k = 0; k < nx; ++k) {
+            s += zk * E((nx - 1 + k) % nx);
+            zk *= z1;
+        }
+        prev = s * inv;
+        E(nx - 1) = prev;
+        for (int i = nx - 2; i >= 0; --i) {
+            prev = E(i) + z1 * prev;
+            E(i) = prev;
+        }
+        scale = T(-6) * z1;
+    } else {
+        const T e0 = G(0), eL = G(nx - 1);
+        E(0) = e0;
+        E(nx - 1) = eL;
+        T dprev = T(0);
+        for (int i = 1; i <= nx - 2; ++i) {
+            T rhs = T(6) * G(i) - dprev;
+            if (i == 1) rhs -= e0;
+            if (i == nx - 2) rhs -= eL;
+            dprev = rhs * T(thomas[i]);
+            E(i) = dprev;
+        }
+        for (int i = nx - 3; i >= 1; --i) E(i) = E(i) - T(thomas[i]) * E(i + 1);
+        em1 = T(2) * E(0) - E(1);
+        eN = T(2) * E(nx - 1) - E(nx - 2);
+        scale = T(1);
+    }
+    const double mc = -c;
+    const double Jd = floor(mc);
+    const long J = (long)Jd;
+    T w[4];
+    cubic_weights(T(mc - Jd), w[0], w[1], w[2], w[3]);
+    for (int i = 0; i < nx; ++i) {
+        T acc = T(0);
+        if constexpr (PER) {
+            for (int k = 0; k < 4; ++k) {
+                long j = ((long)i + J + k - 1) % nx;
+                if (j < 0) j += nx;
+                acc += w[k] * E((int)j);
+            }
+            acc *= scale;
+        } else {
+            const double u = (double)i - c;
+            if (u >= 0.0 && u <= (double)(nx - 1)) {
+                for (int k = 0; k < 4; ++k) {
+                    const long j = (long)i + J + k - 1;
+                    T e = (j >= 0 && j < nx) ? E((int)j)
+                                             : (j == -1 ? em1 : (j == nx ? eN : T(0)));
+                    acc += w[k] * e;
+                }
+            }
+        }
+        out[lm.base + (long)i * lm.stride] = acc;
+    }
+}
+
+template <typename T, int NX, bool PER>
+hipError_t run_reg(const T* in, T* out, int nk, int dim, long nl, double cpp, const double* p,
+                   const double* th, hipStream_t st)
+{
+    const unsigned nb = (unsigned)((nl + 63) / 64);
+    hipLaunchKernelGGL((k_advect_reg<T, NX, PER>), dim3(nb), dim3(64), 0, st, in, out, nk, dim,
+                       nl, cpp, p, th);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool advect_in_registers(int nx, bool periodic, double max_cells)
+{
+    if (!(max_cells <= 1.0)) return false;
+    if (periodic) return nx == 16 || nx == 32 || nx == 48 || nx == 64 || nx == 96 || nx == 128;
+    return nx == 33 || nx == 65 || nx == 129;
+}
+
+template <typename T>
+hipError_t launch_advect(const T* in, T* out, T* work, int nx, int nk, int dim, bool periodic,
+                         double cpp, double max_cells, const double* p_dev,
+                         const double* thomas_dev, hipStream_t st)
+{
+    const long nl = (long)nx * nk * nk;
+    if (nl == 0) return hipSuccess;
+    if (advect_in_registers(nx, periodic, max_cells)) {
+        if (periodic) {
+            switch (nx) {
+            case 16: return run_reg<T, 16, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
+            case 32: return run_reg<T, 32, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
+            case 48: return run_reg<T, 48, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
+            case 64: return run_reg<T, 64, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
+            case 96: return run_reg<T, 96, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
+            case 128: return run_reg<T, 128, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
+            default: break;
+            }
+        } else {
+            switch (nx) {
+            case 33: return run_reg<T, 33, false>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
+            case 65: return run_reg<T, 65, false>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
+            case 129: return run_reg<T, 129, false>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
+            default: break;
+            }
+        }
+    }
+    if (!work) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)((nl + 63) / 64);
+    if (periodic)
+        hipLaunchKernelGGL((k_advect_any<T, true>), dim3(nb), dim3(64), 0, st, in, out, work, nx,
+                           nk, dim, nl, cpp, p_dev, thomas_dev);
+    else
+        hipLaunchKernelGGL((k_advect_any<T, false>), dim3(nb), dim3(64), 0, st, in, out, work, nx,
+                           nk, dim, nl, cpp, p_dev, thomas_dev);
+    return hipGetLastError();
+}
+
+template hipError_t launch_advect<double>(const double*, double*, double*, int, int, int, bool,
+                                          double, double, const double*, const double*,
+                                          hipStream_t);
+template hipError_t launch_advect<float>(const float*, float*, float*, int, int, int, bool, double,
+                                         double, const double*, const double*, hipStream_t);
+
+}  // namespace wig2

@@ -1,0 +1,608 @@
+// C ABI of libwig2 (declared in include/wig2.h): context, tables, the step
+// schedule and the observables.  All time-stepping work runs in the HIP
+// kernels of advect.hip / theta.hip / reduce.hip on the context stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace wig2;
+
+struct wig2_ctx {
+    GridInfo g{};
+    wig2_params prm{};
+    int device = 0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    int elem = 8;
+    long npts = 0;
+    void* f = nullptr;
+    void* k1 = nullptr;
+    void* tmp = nullptr;
+    void* work = nullptr;  // lazily allocated advection scratch
+    double *p_d = nullptr, *w_d = nullptr, *thomas_d = nullptr;
+    double *sig_ext_d = nullptr, *sig1_d = nullptr, *sig2_d = nullptr, *kap_d = nullptr;
+    double *ksem_d = nullptr, *v12pair_d = nullptr, *sintab_d = nullptr;
+    double *mf_dens_d = nullptr, *mf_veff_d = nullptr;
+    double *s0_d = nullptr, *s0b_d = nullptr, *skin_d = nullptr, *s2_d = nullptr;
+    double *rows_d = nullptr, *f1_d = nullptr;
+    int band = 0;
+    bool two_body = false, meanfield = false;
+    std::vector<double> x, p, w, vext_x, v12pair;
+    double pmax = 0.0;
+    bool has_state = false, has_pot = false;
+    int64_t nstep = 0;
+    double t = 0.0;
+    std::string err;
+    // per-kernel-class HIP event timing (wig2_profile)
+    bool prof = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_ev;
+    std::vector<hipEvent_t> ev_pool;
+    double prof_ms[WIG2_PROF_N] = {};
+    int64_t prof_cnt[WIG2_PROF_N] = {};
+};
+
+namespace {
+
+hipEvent_t pool_event(wig2_ctx* c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Wrap one launch of kernel class k in a pair of events when profiling.
+template <typename F>
+hipError_t timed(wig2_ctx* c, int k, F&& launch)
+{
+    if (!c->prof) return launch();
+    hipEvent_t a = pool_event(c), b = pool_event(c);
+    if (!a || !b) return launch();
+    hipEventRecord(a, c->st);
+    hipError_t e = launch();
+    hipEventRecord(b, c->st);
+    c->prof_ev.push_back({k, {a, b}});
+    return e;
+}
+
+int fail(wig2_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? WIG2_ENOMEM : WIG2_EDEVICE,        \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+bool isfin(double v) { return std::isfinite(v); }
+
+template <typename T>
+int dev_alloc(wig2_ctx* c, T** p, size_t n)
+{
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e != hipSuccess) return fail(c, WIG2_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return 0;
+}
+
+int upload(wig2_ctx* c, double* d, const std::vector<double>& h)
+{
+    HIPCHK(c, hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return 0;
+}
+
+bool theta_nk_ok(int nk) { return nk == 16 || nk == 32 || nk == 48 || nk == 64 || nk == 96 || nk == 128; }
+
+// ---- step building blocks -------------------------------------------------
+
+template <typename T>
+hipError_t advect(wig2_ctx* c, int dim, double s, const T* in, T* out)
+{
+    const double cpp = s / (c->g.mass * c->g.dx());
+    const double maxc = std::fabs(cpp) * c->pmax;
+    T* wk = static_cast<T*>(c->work);
+    return launch_advect<T>(in, out, wk, c->g.nx, c->g.nk, dim, c->g.periodic != 0, cpp, maxc, c->p_d,
+                            c->thomas_d, c->st);
+}
+
+template <typename T>
+hipError_t moments(wig2_ctx* c, const T* f, double* s0, double* skin, double* s2, double* rows)
+{
+    return launch_plane_moments<T>(f, c->g.nx, c->g.nk, c->p_d, c->w_d, 0.5 / c->g.mass, s0, skin, s2,
+                                   rows, c->st);
+}
+
+MeanFieldArgs mf_args(wig2_ctx* c)
+{
+    MeanFieldArgs a;
+    a.nx = c->g.nx;
+    a.nk = c->g.nk;
+    a.dx = c->g.dx();
+    a.lambda = c->prm.meanfield_lambda;
+    a.hbar = c->g.hbar;
+    a.xc = c->prm.xc;
+    a.xc_n0 = c->prm.xc_n0;
+    a.n_scale = c->prm.n_scale;
+    a.v12pair = c->v12pair_d;
+    a.sig_ext = c->sig_ext_d;
+    a.sintab = c->sintab_d;
+    a.dens = c->mf_dens_d;
+    a.veff = c->mf_veff_d;
+    return a;
+}
+
+ThetaArgs theta_args(wig2_ctx* c)
+{
+    ThetaArgs a;
+    a.nx = c->g.nx;
+    a.nk = c->g.nk;
+    a.sig1 = c->meanfield ? c->sig1_d : c->sig_ext_d;
+    a.sig2 = c->meanfield ? c->sig2_d : c->sig_ext_d;
+    a.band = c->meanfield ? c->g.nk : c->band;
+    a.kap = c->two_body ? c->kap_d : nullptr;
+    a.ksem = c->g.periodic ? nullptr : c->ksem_d;
+    a.precision = c->prm.precision;
+    return a;
+}
+
+template <typename T>
+hipError_t theta(wig2_ctx* c, const T* u, const T* v, T* out, int mode, double tau)
+{
+    return launch_theta<T>(theta_args(c), u, v, out, mode, tau, c->st);
+}
+
+template <typename T>
+hipError_t update_meanfield(wig2_ctx* c, const T* a, const T* b, double tau_b)
+{
+    hipError_t e = moments<T>(c, a, c->s0_d, nullptr, nullptr, nullptr);
+    if (e != hipSuccess) return e;
+    if (b) {
+        e = moments<T>(c, b, c->s0b_d, nullptr, nullptr, nullptr);
+        if (e != hipSuccess) return e;
+    }
+    return launch_meanfield(mf_args(c), c->s0_d, b ? c->s0b_d : nullptr, tau_b, c->sig1_d, c->sig2_d,
+                            c->st);
+}
+
+template <typename T>
+hipError_t step_once(wig2_ctx* c)
+{
+    T* f = static_cast<T*>(c->f);
+    T* k1 = static_cast<T*>(c->k1);
+    T* tmp = static_cast<T*>(c->tmp);
+    const double tau = c->prm.dt;
+    hipError_t e;
+#define STEPCHK(x)                  \
+    do {                            \
+        e = (x);                    \
+        if (e != hipSuccess) return e; \
+    } while (0)
+    auto ADV = [&](int dim, double sh, const T* in, T* out) {
+        return timed(c, dim == 1 ? WIG2_PROF_ADVECT_X1 : WIG2_PROF_ADVECT_X2,
+                     [&] { return advect<T>(c, dim, sh, in, out); });
+    };
+    auto TH = [&](const T* u, const T* v, T* out, int mode) {
+        return timed(c, mode == 0 ? WIG2_PROF_THETA_STAGE1 : WIG2_PROF_THETA_STAGE2,
+                     [&] { return theta<T>(c, u, v, out, mode, tau); });
+    };
+    auto MF = [&](const T* a, const T* b, double tb) {
+        return timed(c, WIG2_PROF_MEANFIELD, [&] { return update_meanfield<T>(c, a, b, tb); });
+    };
+    if (c->prm.scheme == WIG2_STRANG) {
+        STEPCHK(ADV(1, 0.5 * tau, f, tmp));
+        STEPCHK(ADV(2, 0.5 * tau, tmp, f));
+        if (c->meanfield) STEPCHK(MF(f, nullptr, 0.0));
+        STEPCHK(TH(f, nullptr, k1, 0));
+        STEPCHK(TH(f, k1, f, 1));
+        STEPCHK(ADV(1, 0.5 * tau, f, tmp));
+        STEPCHK(ADV(2, 0.5 * tau, tmp, f));
+    } else {
+        if (c->meanfield) STEPCHK(MF(f, nullptr, 0.0));
+        STEPCHK(TH(f, nullptr, k1, 0));
+        STEPCHK(ADV(1, tau, f, tmp));
+        STEPCHK(ADV(2, tau, tmp, f));
+        STEPCHK(ADV(1, tau, k1, tmp));
+        STEPCHK(ADV(2, tau, tmp, k1));
+        if (c->meanfield) STEPCHK(MF(f, k1, tau));
+        STEPCHK(TH(f, k1, f, 1));
+    }
+#undef STEPCHK
+    return hipSuccess;
+}
+
+int ensure_work(wig2_ctx* c)
+{
+    const double s = c->prm.scheme == WIG2_STRANG ? 0.5 * c->prm.dt : c->prm.dt;
+    const double maxc = s * c->pmax / (c->g.mass * c->g.dx());
+    if (c->work || advect_in_registers(c->g.nx, c->g.periodic != 0, maxc)) return 0;
+    HIPCHK(c, hipMalloc(&c->work, (size_t)c->npts * c->elem));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wig2_strerror(int code)
+{
+    switch (code) {
+    case WIG2_OK: return "ok";
+    case WIG2_EINVAL: return "invalid argument";
+    case WIG2_ENOMEM: return "out of memory";
+    case WIG2_EDEVICE: return "HIP device error";
+    case WIG2_ESTATE: return "call out of order";
+    case WIG2_ENOTSUP: return "not supported";
+    case WIG2_ENUMERIC: return "non-finite value";
+    default: return "unknown error";
+    }
+}
+
+const char* wig2_last_error(const wig2_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int wig2_create(const wig2_grid* grid, const wig2_params* prm, void* hip_stream, wig2_ctx** out)
+{
+    if (!grid || !prm || !out) return WIG2_EINVAL;
+    *out = nullptr;
+    const wig2_grid& G = *grid;
+    const wig2_params& P = *prm;
+    if (G.nx < 4 || G.nk < 2 || !isfin(G.x_min) || !isfin(G.x_max) || !(G.x_max > G.x_min))
+        return WIG2_EINVAL;
+    if (!isfin(P.hbar) || !isfin(P.mass) || !isfin(P.dt) || !(P.hbar > 0) || !(P.mass > 0) ||
+        !(P.dt > 0) || !isfin(P.meanfield_lambda))
+        return WIG2_EINVAL;
+    if (P.scheme != WIG2_STRANG && P.scheme != WIG2_LAWSON_PC) return WIG2_EINVAL;
+    if (P.precision != WIG2_FP64 && P.precision != WIG2_FP32 && P.precision != WIG2_BF16X2)
+        return WIG2_EINVAL;
+    if (!G.periodic) {
+        if (G.sem_cells < 1 || G.nk % G.sem_cells != 0 || !isfin(G.k_max) || !(G.k_max > 0))
+            return WIG2_EINVAL;
+    }
+    if (P.xc && (!isfin(P.xc_n0) || !isfin(P.n_scale))) return WIG2_EINVAL;
+    if (!theta_nk_ok(G.nk)) return WIG2_ENOTSUP;
+    if (P.precision == WIG2_BF16X2 && G.nk % 32 != 0) return WIG2_ENOTSUP;
+    if (!G.periodic && (P.meanfield_lambda != 0.0 || P.xc)) return WIG2_ENOTSUP;
+    if (!G.periodic && P.precision == WIG2_BF16X2) return WIG2_ENOTSUP;
+
+    wig2_ctx* c = new (std::nothrow) wig2_ctx();
+    if (!c) return WIG2_ENOMEM;
+    c->g = GridInfo{G.nx, G.nk, G.periodic ? 1 : 0, G.periodic ? 1 : G.sem_cells, G.x_min, G.x_max,
+                    G.k_max, P.hbar, P.mass};
+    c->prm = P;
+    c->elem = P.precision == WIG2_FP64 ? 8 : 4;
+    c->npts = (long)G.nx * G.nx * G.nk * G.nk;
+    c->meanfield = P.meanfield_lambda != 0.0 || P.xc;
+    auto bail = [&](int code) {
+        wig2_destroy(c);
+        return code;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(WIG2_EDEVICE);
+    if (hip_stream) {
+        c->st = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess) return bail(WIG2_EDEVICE);
+        c->own_stream = true;
+    }
+    const size_t bytes = (size_t)c->npts * c->elem;
+    if (hipMalloc(&c->f, bytes) != hipSuccess || hipMalloc(&c->k1, bytes) != hipSuccess ||
+        hipMalloc(&c->tmp, bytes) != hipSuccess)
+        return bail(WIG2_ENOMEM);
+    const int nx = G.nx, nk = G.nk;
+    const size_t np = (size_t)nx * nx;
+    if (dev_alloc(c, &c->p_d, nk) || dev_alloc(c, &c->w_d, nk) || dev_alloc(c, &c->thomas_d, nx) ||
+        dev_alloc(c, &c->sig_ext_d, (size_t)nx * nk) || dev_alloc(c, &c->sig1_d, (size_t)nx * nk) ||
+        dev_alloc(c, &c->sig2_d, (size_t)nx * nk) || dev_alloc(c, &c->kap_d, (size_t)nx * nk) ||
+        dev_alloc(c, &c->v12pair_d, np) || dev_alloc(c, &c->sintab_d, (size_t)nk * nx) ||
+        dev_alloc(c, &c->mf_dens_d, 2 * (size_t)nx) || dev_alloc(c, &c->mf_veff_d, 2 * (size_t)nx) ||
+        dev_alloc(c, &c->s0_d, np) || dev_alloc(c, &c->s0b_d, np) || dev_alloc(c, &c->skin_d, np) ||
+        dev_alloc(c, &c->s2_d, np) || dev_alloc(c, &c->rows_d, np * nk) ||
+        dev_alloc(c, &c->f1_d, (size_t)nx * nk))
+        return bail(WIG2_ENOMEM);
+    if (!G.periodic && dev_alloc(c, &c->ksem_d, (size_t)nx * nk * nk)) return bail(WIG2_ENOMEM);
+
+    host_nodes(c->g, c->x, c->p, c->w);
+    c->pmax = 0.0;
+    for (double v : c->p) c->pmax = std::max(c->pmax, std::fabs(v));
+    std::vector<double> th(nx, 0.0);
+    {
+        double m = 0.0;
+        for (int i = 1; i < nx - 1; ++i) {
+            m = 1.0 / (4.0 - m);
+            th[i] = m;
+        }
+    }
+    std::vector<double> sintab((size_t)nk * nx);
+    for (int m = 0; m < nk; ++m)
+        for (int d = 0; d < nx; ++d)
+            sintab[(size_t)m * nx + d] = std::sin(2.0 * 3.141592653589793238462643383279502884 * m * d / nx);
+    if (upload(c, c->p_d, c->p) || upload(c, c->w_d, c->w) || upload(c, c->thomas_d, th) ||
+        upload(c, c->sintab_d, sintab))
+        return bail(WIG2_EDEVICE);
+    if (ensure_work(c)) return bail(WIG2_ENOMEM);
+    *out = c;
+    return WIG2_OK;
+}
+
+void wig2_destroy(wig2_ctx* c)
+{
+    if (!c) return;
+    if (c->st) hipStreamSynchronize(c->st);
+    void* bufs[] = {c->f, c->k1, c->tmp, c->work, c->p_d, c->w_d, c->thomas_d, c->sig_ext_d, c->sig1_d,
+                    c->sig2_d, c->kap_d, c->ksem_d, c->v12pair_d, c->sintab_d, c->mf_dens_d,
+                    c->mf_veff_d, c->s0_d, c->s0b_d, c->skin_d, c->s2_d, c->rows_d, c->f1_d};
+    for (void* b : bufs)
+        if (b) hipFree(b);
+    for (auto& pe : c->prof_ev) {
+        hipEventDestroy(pe.second.first);
+        hipEventDestroy(pe.second.second);
+    }
+    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    if (c->own_stream && c->st) hipStreamDestroy(c->st);
+    delete c;
+}
+
+int wig2_set_potentials(wig2_ctx* c, wig2_fn1 v_ext, wig2_fn1 v12, void* user)
+{
+    if (!c) return WIG2_EINVAL;
+    const GridInfo& g = c->g;
+    const int nx = g.nx, nk = g.nk;
+    const double L = g.L();
+    auto V = [&](wig2_fn1 fn, double x) { return fn ? fn(x, user) : 0.0; };
+    if (!g.periodic && v12) return fail(c, WIG2_ENOTSUP, "pair potential on a box needs the two-body SEM operator");
+    c->vext_x.resize(nx);
+    for (int i = 0; i < nx; ++i) c->vext_x[i] = V(v_ext, c->x[i]);
+    c->v12pair.assign((size_t)nx * nx, 0.0);
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < nx; ++j) {
+            double r = c->x[i] - c->x[j];
+            if (g.periodic) r -= L * std::floor((r + 0.5 * L) / L);
+            c->v12pair[(size_t)i * nx + j] = V(v12, r);
+        }
+    for (double v : c->vext_x)
+        if (!isfin(v)) return fail(c, WIG2_EINVAL, "V_ext returned a non-finite value");
+    for (double v : c->v12pair)
+        if (!isfin(v)) return fail(c, WIG2_EINVAL, "V12 returned a non-finite value");
+    if (g.periodic) {
+        std::vector<double> vy(2 * nk), vr(2 * nk), s, vh, kap;
+        for (int j = 0; j < 2 * nk; ++j) {
+            vy[j] = V(v_ext, g.x_min + L * j / (2 * nk));
+            vr[j] = V(v12, -0.5 * L + L * j / (2 * nk));
+            if (!isfin(vy[j]) || !isfin(vr[j])) return fail(c, WIG2_EINVAL, "non-finite potential sample");
+        }
+        host_symbol_ext(g, vy, s);
+        host_pair_kernel(g, vr, vh, kap);
+        double smax = 0.0;
+        for (double v : s) smax = std::max(smax, std::fabs(v));
+        c->band = 0;
+        for (int m = 1; m < nk; ++m)
+            for (int i = 0; i < nx; ++i)
+                if (std::fabs(s[(size_t)i * nk + m]) > 1e-13 * smax) c->band = std::max(c->band, m);
+        c->two_body = false;
+        for (int m = 1; m < nk; ++m)
+            if (vh[m] != 0.0) c->two_body = true;
+        if (upload(c, c->sig_ext_d, s) || upload(c, c->kap_d, kap)) return WIG2_EDEVICE;
+        if (c->meanfield) {
+            if (upload(c, c->sig1_d, s) || upload(c, c->sig2_d, s)) return WIG2_EDEVICE;
+        }
+    } else {
+        std::vector<double> K;
+        host_sem_matrix(g, c->vext_x, K);
+        if (upload(c, c->ksem_d, K)) return WIG2_EDEVICE;
+        c->two_body = false;
+        c->band = nk;
+    }
+    if (upload(c, c->v12pair_d, c->v12pair)) return WIG2_EDEVICE;
+    c->has_pot = true;
+    c->err.clear();
+    return WIG2_OK;
+}
+
+int wig2_set_state(wig2_ctx* c, const double* fh)
+{
+    if (!c || !fh) return WIG2_EINVAL;
+    if (c->elem == 8) {
+        HIPCHK(c, hipMemcpyAsync(c->f, fh, (size_t)c->npts * 8, hipMemcpyHostToDevice, c->st));
+    } else {
+        std::vector<float> tmp(c->npts);
+        for (long i = 0; i < c->npts; ++i) tmp[i] = (float)fh[i];
+        HIPCHK(c, hipMemcpyAsync(c->f, tmp.data(), (size_t)c->npts * 4, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->has_state = true;
+    c->nstep = 0;
+    c->t = 0.0;
+    c->err.clear();
+    return WIG2_OK;
+}
+
+int wig2_get_state(wig2_ctx* c, double* fh)
+{
+    if (!c || !fh) return WIG2_EINVAL;
+    if (!c->has_state) return fail(c, WIG2_ESTATE, "no state");
+    if (c->elem == 8) {
+        HIPCHK(c, hipMemcpyAsync(fh, c->f, (size_t)c->npts * 8, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+    } else {
+        std::vector<float> tmp(c->npts);
+        HIPCHK(c, hipMemcpyAsync(tmp.data(), c->f, (size_t)c->npts * 4, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+        for (long i = 0; i < c->npts; ++i) fh[i] = tmp[i];
+    }
+    return WIG2_OK;
+}
+
+int wig2_state_buffer(wig2_ctx* c, void** fd, int32_t* eb)
+{
+    if (!c || !fd) return WIG2_EINVAL;
+    *fd = c->f;
+    if (eb) *eb = c->elem;
+    return WIG2_OK;
+}
+
+int wig2_state_written(wig2_ctx* c)
+{
+    if (!c) return WIG2_EINVAL;
+    c->has_state = true;
+    c->nstep = 0;
+    c->t = 0.0;
+    return WIG2_OK;
+}
+
+int wig2_step(wig2_ctx* c, int64_t n)
+{
+    if (!c || n < 0) return WIG2_EINVAL;
+    if (!c->has_state || !c->has_pot) return fail(c, WIG2_ESTATE, "set the state and the potentials first");
+    for (int64_t k = 0; k < n; ++k) {
+        hipError_t e = c->elem == 8 ? step_once<double>(c) : step_once<float>(c);
+        if (e != hipSuccess) return fail(c, e == hipErrorNotSupported ? WIG2_ENOTSUP : WIG2_EDEVICE,
+                                         std::string("step: ") + hipGetErrorString(e));
+        c->nstep++;
+        c->t += c->prm.dt;
+    }
+    return WIG2_OK;
+}
+
+int wig2_theta(wig2_ctx* c, const void* in, void* out)
+{
+    if (!c || !in || !out) return WIG2_EINVAL;
+    if (!c->has_pot) return fail(c, WIG2_ESTATE, "set the potentials first");
+    hipError_t e;
+    if (c->elem == 8) {
+        if (c->meanfield && (e = update_meanfield<double>(c, (const double*)in, nullptr, 0.0)) != hipSuccess)
+            return fail(c, WIG2_EDEVICE, hipGetErrorString(e));
+        e = theta<double>(c, (const double*)in, nullptr, (double*)out, 0, c->prm.dt);
+    } else {
+        if (c->meanfield && (e = update_meanfield<float>(c, (const float*)in, nullptr, 0.0)) != hipSuccess)
+            return fail(c, WIG2_EDEVICE, hipGetErrorString(e));
+        e = theta<float>(c, (const float*)in, nullptr, (float*)out, 0, c->prm.dt);
+    }
+    if (e != hipSuccess) return fail(c, e == hipErrorNotSupported ? WIG2_ENOTSUP : WIG2_EDEVICE,
+                                     std::string("theta: ") + hipGetErrorString(e));
+    return WIG2_OK;
+}
+
+int wig2_advect(wig2_ctx* c, int32_t dim, double s, const void* in, void* out)
+{
+    if (!c || !in || !out || in == out || (dim != 1 && dim != 2) || !isfin(s)) return WIG2_EINVAL;
+    const double maxc = std::fabs(s) * c->pmax / (c->g.mass * c->g.dx());
+    if (!advect_in_registers(c->g.nx, c->g.periodic != 0, maxc) && !c->work)
+        HIPCHK(c, hipMalloc(&c->work, (size_t)c->npts * c->elem));
+    hipError_t e = c->elem == 8 ? advect<double>(c, dim, s, (const double*)in, (double*)out)
+                                : advect<float>(c, dim, s, (const float*)in, (float*)out);
+    if (e != hipSuccess) return fail(c, WIG2_EDEVICE, std::string("advect: ") + hipGetErrorString(e));
+    return WIG2_OK;
+}
+
+int wig2_nodes(const wig2_ctx* c, double* x, double* p, double* w)
+{
+    if (!c) return WIG2_EINVAL;
+    if (x) std::copy(c->x.begin(), c->x.end(), x);
+    if (p) std::copy(c->p.begin(), c->p.end(), p);
+    if (w) std::copy(c->w.begin(), c->w.end(), w);
+    return WIG2_OK;
+}
+
+int wig2_profile(wig2_ctx* c, int32_t enable)
+{
+    if (!c) return WIG2_EINVAL;
+    c->prof = enable != 0;
+    return WIG2_OK;
+}
+
+int wig2_profile_read(wig2_ctx* c, double* ms, int64_t* counts, int32_t reset)
+{
+    if (!c) return WIG2_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (auto& pe : c->prof_ev) {
+        float v = 0.f;
+        if (hipEventElapsedTime(&v, pe.second.first, pe.second.second) == hipSuccess) {
+            c->prof_ms[pe.first] += v;
+            c->prof_cnt[pe.first] += 1;
+        }
+        c->ev_pool.push_back(pe.second.first);
+        c->ev_pool.push_back(pe.second.second);
+    }
+    c->prof_ev.clear();
+    for (int k = 0; k < WIG2_PROF_N; ++k) {
+        if (ms) ms[k] = c->prof_ms[k];
+        if (counts) counts[k] = c->prof_cnt[k];
+        if (reset) {
+            c->prof_ms[k] = 0.0;
+            c->prof_cnt[k] = 0;
+        }
+    }
+    return WIG2_OK;
+}
+
+int wig2_band(const wig2_ctx* c)
+{
+    if (!c) return WIG2_EINVAL;
+    return c->meanfield ? c->g.nk - 1 : std::min(c->band, c->g.nk - 1);
+}
+
+int wig2_observables(wig2_ctx* c, wig2_obs* o, double* n1, double* n12, double* f1)
+{
+    if (!c || !o) return WIG2_EINVAL;
+    if (!c->has_state) return fail(c, WIG2_ESTATE, "no state");
+    const int nx = c->g.nx, nk = c->g.nk;
+    const size_t np = (size_t)nx * nx;
+    hipError_t e = c->elem == 8
+                       ? moments<double>(c, (const double*)c->f, c->s0_d, c->skin_d, c->s2_d, c->rows_d)
+                       : moments<float>(c, (const float*)c->f, c->s0_d, c->skin_d, c->s2_d, c->rows_d);
+    if (e != hipSuccess) return fail(c, WIG2_EDEVICE, hipGetErrorString(e));
+    const double dx = c->g.dx();
+    HIPCHK(c, launch_reduce_rows(c->rows_d, nx, nk, dx, c->f1_d, c->st));
+    std::vector<double> s0(np), sk(np), s2(np), hf1((size_t)nx * nk);
+    HIPCHK(c, hipMemcpyAsync(s0.data(), c->s0_d, np * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(sk.data(), c->skin_d, np * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(s2.data(), c->s2_d, np * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(hf1.data(), c->f1_d, hf1.size() * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    double mass = 0.0, en = 0.0, l2 = 0.0;
+    for (int i1 = 0; i1 < nx; ++i1)
+        for (int i2 = 0; i2 < nx; ++i2) {
+            const size_t q = (size_t)i1 * nx + i2;
+            const double vpot = (c->vext_x.empty() ? 0.0 : c->vext_x[i1] + c->vext_x[i2]) +
+                                (c->v12pair.empty() ? 0.0 : c->v12pair[q]);
+            mass += s0[q];
+            en += sk[q] + vpot * s0[q];
+            l2 += s2[q];
+        }
+    o->step = c->nstep;
+    o->t = c->t;
+    o->mass = dx * dx * mass;
+    o->energy = dx * dx * en;
+    o->l2 = dx * dx * l2;
+    std::vector<double> occ;
+    o->entropy_vn = host_entropy(c->g, hf1, occ);
+    o->fallbacks = 0;
+    if (n12) std::copy(s0.begin(), s0.end(), n12);
+    if (n1)
+        for (int i1 = 0; i1 < nx; ++i1) {
+            double s = 0.0;
+            for (int i2 = 0; i2 < nx; ++i2) s += s0[(size_t)i1 * nx + i2];
+            n1[i1] = dx * s;
+        }
+    if (f1) std::copy(hf1.begin(), hf1.end(), f1);
+    if (!isfin(o->mass) || !isfin(o->energy) || !isfin(o->l2))
+        return fail(c, WIG2_ENUMERIC, "non-finite observable");
+    return WIG2_OK;
+}
+
+}  // extern "C"

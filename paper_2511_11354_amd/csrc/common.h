@@ -1,0 +1,106 @@
+// Internal declarations shared by the HIP translation units of libwig2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/wig2.h"
+
+namespace wig2 {
+
+// Largest momentum-plane size handled by the fused Theta kernel (one plane in
+// LDS: 128 x 129 FP64 = 129 KB of the 160 KB per CU).
+constexpr int kMaxThetaNk = 128;
+
+// ---------------------------------------------------------------------------
+// Host-side symbol tables (tables.cpp).  All FP64.
+// ---------------------------------------------------------------------------
+struct GridInfo {
+    int nx, nk, periodic, cells;
+    double x_min, x_max, k_max, hbar, mass;
+    double L() const { return x_max - x_min; }
+    double dx() const { return periodic ? L() / nx : L() / (nx - 1); }
+};
+
+void host_nodes(const GridInfo& g, std::vector<double>& x, std::vector<double>& p,
+                std::vector<double>& w);
+// Periodic single-body symbol s[i][m] = (2/hbar) sig_m(x_i) from V at 2nk
+// points y_j = x_min + j L/(2 nk).
+void host_symbol_ext(const GridInfo& g, const std::vector<double>& v_y, std::vector<double>& s);
+// Periodic pair kernel kap[l][m] = (2/hbar) Vhat_m sin(2 pi m l / nx), from
+// V12 at r_j = -L/2 + j L/(2nk).
+void host_pair_kernel(const GridInfo& g, const std::vector<double>& v12_r,
+                      std::vector<double>& vhat, std::vector<double>& kap);
+// Box single-body SEM matrices K[i][n][n'] from V at the x nodes.
+void host_sem_matrix(const GridInfo& g, const std::vector<double>& v_x, std::vector<double>& K);
+// Occupations of the trace-one 1-RDM built from f1 on the even sub-lattice.
+double host_entropy(const GridInfo& g, const std::vector<double>& f1, std::vector<double>& occ);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers.  T is double or float.
+// ---------------------------------------------------------------------------
+
+// One spline sweep along x_dim: out(x, p) = in(x - s p_dim / m, p).
+// cells_per_p = s / (m dx); p_dev[nk] momentum nodes; work: state-sized scratch
+// used only when the register-resident path does not cover (nx, shift).
+// thomas_dev: Thomas multipliers for the box spline (nx entries).
+// True when the register-resident sweep covers (nx, displacement); otherwise
+// launch_advect needs the state-sized `work` array.
+bool advect_in_registers(int nx, bool periodic, double max_cells);
+template <typename T>
+hipError_t launch_advect(const T* in, T* out, T* work, int nx, int nk, int dim, bool periodic,
+                         double cells_per_p, double max_cells, const double* p_dev,
+                         const double* thomas_dev, hipStream_t st);
+
+// Theta application on all nx*nx planes.
+//   mode 0: out = Theta[u]
+//   mode 1: out = u + tau/2 (v + Theta[u + tau v])   (out may equal u)
+// sig1, sig2: [nx][nk] scaled single-body symbols (torus), band: largest m
+// with a non-zero single-body symbol (nk-1 or more: dense).
+// kap: [nx][nk] pair kernel (torus, NULL = no two-body term).
+// ksem: [nx][nk][nk] single-body matrices (box; replaces sig1/sig2).
+struct ThetaArgs {
+    int nx, nk;
+    const double* sig1;
+    const double* sig2;
+    int band;
+    const double* kap;
+    const double* ksem;
+    int precision;  // WIG2_FP64 / WIG2_FP32 / WIG2_BF16X2
+};
+template <typename T>
+hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, double tau,
+                        hipStream_t st);
+
+// Per-plane moments: s0 = sum w w f, skin = sum w w f (p1^2+p2^2)/2m,
+// s2 = sum w w f^2 (each [nx*nx]); rows[pl][n1] = sum_n2 w f (optional).
+template <typename T>
+hipError_t launch_plane_moments(const T* f, int nx, int nk, const double* p_dev,
+                                const double* w_dev, double inv2m, double* s0, double* skin,
+                                double* s2, double* rows, hipStream_t st);
+// f1[i1][n1] = dx sum_i2 rows[i1*nx+i2][n1].
+hipError_t launch_reduce_rows(const double* rows, int nx, int nk, double dx, double* f1,
+                              hipStream_t st);
+// Mean-field symbols from the plane sums s0 (torus):
+//   n_1 = dx sum_i2 s0, n_2 = dx sum_i1 s0,
+//   V_j = lambda dx sum V12pair n_j + xc terms,
+//   sig_j[i][m] = sig_ext[i][m] + (2/hbar)(1/nx) sum_k V_j(x_k) sin(2 pi m (i-k)/nx), 2m < nx.
+// If s0b != NULL the density is that of s0 + tau_b * s0b.
+struct MeanFieldArgs {
+    int nx, nk;
+    double dx, lambda, hbar;
+    int xc;
+    double xc_n0, n_scale;
+    const double* v12pair;  // [nx][nx]
+    const double* sig_ext;  // [nx][nk], scaled by 2/hbar
+    const double* sintab;   // [nk][nx] sin(2 pi m d / nx)
+    double* dens;           // [2][nx] scratch
+    double* veff;           // [2][nx] scratch
+};
+hipError_t launch_meanfield(const MeanFieldArgs& a, const double* s0, const double* s0b,
+                            double tau_b, double* sig1, double* sig2, hipStream_t st);
+
+}  // namespace wig2

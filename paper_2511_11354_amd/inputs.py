@@ -113,21 +113,21 @@ def mixture_params(seed: int):
 
 def mixture(x, p, seed: int, sigma=1.0, hbar=1.0, period=None, dtype=np.float64):
     """Exchange-symmetric incoherent mixture
-      f = sum_{i != j} w_i w_j G_i(x1,p1) G_j(x2,p2) / sum_{i != j} w_i w_j."""
+      f = sum_{i != j} w_i w_j G_i(x1,p1) G_j(x2,p2) / sum_{i != j} w_i w_j,
+    assembled as (A x A - sum_i w_i^2 G_i x G_i) / norm with A = sum_i w_i G_i,
+    one x1 slab at a time."""
     a, q, w = mixture_params(seed)
     G = [packet(x, p, a[j], q[j], sigma, hbar, period) for j in range(len(a))]
-    nx, nk = G[0].shape
-    f = np.zeros((nx, nx, nk, nk), dtype=dtype)
-    norm = 0.0
-    for i in range(len(a)):
+    A = sum(w[j] * G[j] for j in range(len(a)))
+    norm = float(w.sum() ** 2 - (w**2).sum())
+    nx, nk = A.shape
+    f = np.empty((nx, nx, nk, nk), dtype=dtype)
+    for i1 in range(nx):
+        slab = A[i1][None, :, None] * A[:, None, :]
         for j in range(len(a)):
-            if i == j:
-                continue
-            c = w[i] * w[j]
-            norm += c
-            f += (c * np.einsum("ac,bd->abcd", G[i], G[j])).astype(dtype)
-    f /= norm
-    return np.ascontiguousarray(f)
+            slab -= (w[j] ** 2) * G[j][i1][None, :, None] * G[j][:, None, :]
+        f[i1] = slab / norm
+    return f
 
 
 def random_field(shape, seed: int, dtype=np.float64):

@@ -1,0 +1,221 @@
+"""ctypes binding of libwig2 (C ABI in include/wig2.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device buffers may be torch tensors (``.data_ptr()`` is passed through); torch
+is used for device memory and streams, nothing else.  Loading fails loudly if
+the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwig2.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOTSUP, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
+STRANG, LAWSON_PC = 0, 1
+FP64, FP32, BF16X2 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16X2}
+SCHEMES = {"strang": STRANG, "lawson": LAWSON_PC}
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nk", ctypes.c_int32), ("periodic", ctypes.c_int32),
+                ("sem_cells", ctypes.c_int32), ("x_min", ctypes.c_double),
+                ("x_max", ctypes.c_double), ("k_max", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("hbar", ctypes.c_double), ("mass", ctypes.c_double), ("dt", ctypes.c_double),
+                ("scheme", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("meanfield_lambda", ctypes.c_double), ("xc", ctypes.c_int32),
+                ("xc_n0", ctypes.c_double), ("n_scale", ctypes.c_double)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("t", ctypes.c_double), ("mass", ctypes.c_double),
+                ("energy", ctypes.c_double), ("l2", ctypes.c_double),
+                ("entropy_vn", ctypes.c_double), ("fallbacks", ctypes.c_int32)]
+
+
+PROF_NAMES = ("advect_x1", "advect_x2", "theta_stage1", "theta_stage2", "meanfield")
+
+FN1 = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_double, ctypes.c_void_p)
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+# name -> (argtypes, restype)
+SIGNATURES = {
+    "wig2_create": ([ctypes.POINTER(Grid), ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp)],
+                    ctypes.c_int),
+    "wig2_set_potentials": ([_vp, FN1, FN1, _vp], ctypes.c_int),
+    "wig2_set_state": ([_vp, _dp], ctypes.c_int),
+    "wig2_get_state": ([_vp, _dp], ctypes.c_int),
+    "wig2_state_buffer": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "wig2_state_written": ([_vp], ctypes.c_int),
+    "wig2_step": ([_vp, ctypes.c_int64], ctypes.c_int),
+    "wig2_observables": ([_vp, ctypes.POINTER(Obs), _dp, _dp, _dp], ctypes.c_int),
+    "wig2_theta": ([_vp, _vp, _vp], ctypes.c_int),
+    "wig2_advect": ([_vp, ctypes.c_int32, ctypes.c_double, _vp, _vp], ctypes.c_int),
+    "wig2_nodes": ([_vp, _dp, _dp, _dp], ctypes.c_int),
+    "wig2_profile": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "wig2_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32], ctypes.c_int),
+    "wig2_band": ([_vp], ctypes.c_int),
+    "wig2_destroy": ([_vp], None),
+    "wig2_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "wig2_last_error": ([_vp], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libwig2.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2511_11354_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+class Wig2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data_as(_dp)
+    return a
+
+
+def _dev(t):
+    """Device pointer of a torch tensor (or an int address)."""
+    if hasattr(t, "data_ptr"):
+        assert t.is_cuda and t.is_contiguous()
+        return ctypes.c_void_p(t.data_ptr())
+    return ctypes.c_void_p(int(t))
+
+
+class Solver:
+    """One context: grid, parameters, potentials and the device-resident state."""
+
+    def __init__(self, nx, nk, *, periodic=True, sem_cells=1, x_min=-10.0, x_max=10.0,
+                 k_max=0.0, hbar=1.0, mass=1.0, dt=0.01, scheme="strang", precision="fp64",
+                 meanfield_lambda=0.0, xc=False, xc_n0=1.0, n_scale=1.0, stream=None):
+        self._L = lib()
+        self.grid = Grid(nx, nk, int(periodic), sem_cells, x_min, x_max, k_max)
+        self.params = Params(hbar, mass, dt, SCHEMES[scheme], PRECISIONS[precision],
+                             meanfield_lambda, int(xc), xc_n0, n_scale)
+        self.nx, self.nk = nx, nk
+        self.shape = (nx, nx, nk, nk)
+        self.precision = precision
+        self._cbs = []
+        h = ctypes.c_void_p()
+        s = None if stream is None else ctypes.c_void_p(int(stream))
+        rc = self._L.wig2_create(ctypes.byref(self.grid), ctypes.byref(self.params), s,
+                                 ctypes.byref(h))
+        if rc != OK:
+            raise Wig2Error(rc, f"wig2_create: {self._L.wig2_strerror(rc).decode()}")
+        self._h = h
+
+    # -- helpers ----------------------------------------------------------------
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = self._L.wig2_last_error(self._h).decode() or self._L.wig2_strerror(rc).decode()
+            raise Wig2Error(rc, f"{what}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.wig2_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- API --------------------------------------------------------------------
+    def set_potentials(self, v_ext=None, v12=None):
+        cb = lambda fn: FN1(0) if fn is None else FN1(lambda x, u: float(fn(x)))
+        a, b = cb(v_ext), cb(v12)
+        self._cbs = [a, b]
+        self._check(self._L.wig2_set_potentials(self._h, a, b, None), "wig2_set_potentials")
+
+    def set_state(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == self.shape
+        self._check(self._L.wig2_set_state(self._h, _ptr(f)), "wig2_set_state")
+
+    def get_state(self):
+        f = np.empty(self.shape, dtype=np.float64)
+        self._check(self._L.wig2_get_state(self._h, _ptr(f)), "wig2_get_state")
+        return f
+
+    def state_buffer(self):
+        p = ctypes.c_void_p()
+        eb = ctypes.c_int32()
+        self._check(self._L.wig2_state_buffer(self._h, ctypes.byref(p), ctypes.byref(eb)),
+                    "wig2_state_buffer")
+        return p.value, eb.value
+
+    def state_written(self):
+        self._check(self._L.wig2_state_written(self._h), "wig2_state_written")
+
+    def step(self, n=1):
+        self._check(self._L.wig2_step(self._h, int(n)), "wig2_step")
+
+    def observables(self):
+        o = Obs()
+        n1 = np.zeros(self.nx)
+        n12 = np.zeros((self.nx, self.nx))
+        f1 = np.zeros((self.nx, self.nk))
+        self._check(self._L.wig2_observables(self._h, ctypes.byref(o), _ptr(n1), _ptr(n12),
+                                             _ptr(f1)), "wig2_observables")
+        return {"step": o.step, "t": o.t, "mass": o.mass, "energy": o.energy, "l2": o.l2,
+                "entropy": o.entropy_vn, "fallbacks": o.fallbacks, "n1": n1, "n12": n12, "f1": f1}
+
+    def theta(self, f_in, f_out):
+        self._check(self._L.wig2_theta(self._h, _dev(f_in), _dev(f_out)), "wig2_theta")
+
+    def advect(self, dim, s, f_in, f_out):
+        self._check(self._L.wig2_advect(self._h, int(dim), float(s), _dev(f_in), _dev(f_out)),
+                    "wig2_advect")
+
+    def profile(self, enable=True):
+        self._check(self._L.wig2_profile(self._h, int(enable)), "wig2_profile")
+
+    def profile_read(self, reset=True):
+        ms = np.zeros(len(PROF_NAMES))
+        cnt = (ctypes.c_int64 * len(PROF_NAMES))()
+        self._check(self._L.wig2_profile_read(self._h, _ptr(ms), cnt, int(reset)),
+                    "wig2_profile_read")
+        return {n: (float(ms[i]), int(cnt[i])) for i, n in enumerate(PROF_NAMES)}
+
+    def band(self):
+        b = self._L.wig2_band(self._h)
+        if b < 0:
+            self._check(b, "wig2_band")
+        return b
+
+    def nodes(self):
+        x = np.zeros(self.nx)
+        p = np.zeros(self.nk)
+        w = np.zeros(self.nk)
+        self._check(self._L.wig2_nodes(self._h, _ptr(x), _ptr(p), _ptr(w)), "wig2_nodes")
+        return x, p, w

@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+FP64 bar: eps_inf = max|f - f_ref| / max|f_ref| <= 1e-12 (single operator
+applications, single sweeps, 1 and 20 whole steps).  FP32 and split-BF16
+forms state their own error bound here.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2511_11354_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def W():
+    from paper_2511_11354_amd import wig2
+
+    return wig2
+
+
+def eps_inf(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def make(orc, nx, nk, *, periodic=True, cells=1, x_min=-10.0, x_max=10.0, k_max=0.0, hbar=1.0,
+         mass=1.0, dt=0.01, scheme="strang", precision="fp64", vext=None, v12=None, **kw):
+    s = W().Solver(nx, nk, periodic=periodic, sem_cells=cells, x_min=x_min, x_max=x_max,
+                   k_max=k_max, hbar=hbar, mass=mass, dt=dt, scheme=scheme, precision=precision,
+                   **kw)
+    s.set_potentials(vext, v12)
+    g = orc.grid(nx, nk, periodic, cells, x_min, x_max, k_max, hbar, mass)
+    return s, g
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+# --------------------------------------------------------------------------
+# Theta
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nx,nk,pot", [
+    (8, 16, "cos"), (12, 32, "cos"), (6, 48, "dw"), (5, 64, "cos"), (4, 96, "dw"), (3, 128, "cos"),
+])
+def test_theta_fp64_matches_oracle(orc, nx, nk, pot):
+    vext = I.cosine(0.5, 20.0) if pot == "cos" else I.double_well()
+    v12 = I.smoothed_coulomb(1.3, 1.0)
+    s, g = make(orc, nx, nk, vext=vext, v12=v12)
+    f = I.random_field((nx, nx, nk, nk), seed=nx * 100 + nk)
+    tb = orc.tables(g, vext, v12)
+    ref = orc.theta_periodic(g, tb["sig_ext"], tb["sig_ext"], tb["vhat12"], f, True)
+    out = torch.empty((nx, nx, nk, nk), dtype=torch.float64, device="cuda")
+    s.theta(dev(f), out)
+    torch.cuda.synchronize()
+    e = eps_inf(host(out), ref)
+    print(f"theta nx={nx} nk={nk} {pot}: eps_inf={e:.3e}")
+    assert e <= 1e-12
+
+
+def test_theta_single_body_closed_form(orc):
+    """Sec. 5.1.1 closed form through the GPU path, independent of the oracle:
+    V = (2pi)^{-1/2} e^{-(x+r0)^2/2} on both particles of
+    f = pi^-2 e^{-(x1+r0)^2/2 - 2p1^2 - (x2+r0)^2/2 - 2p2^2}  (L = 40, nk = 128)."""
+    r0 = 1.0
+    s, g = make(orc, 8, 128, x_min=-20.0, x_max=20.0, vext=I.gaussian_well(r0))
+    x, p, _ = s.nodes()
+    X1, X2 = x[:, None, None, None], x[None, :, None, None]
+    P1, P2 = p[None, None, :, None], p[None, None, None, :]
+    f = np.pi**-2 * np.exp(-(X1 + r0) ** 2 / 2 - 2 * P1**2 - (X2 + r0) ** 2 / 2 - 2 * P2**2)
+    ex = (np.pi**-2.5 * np.exp(-3 * (X1 + r0) ** 2 / 4 - P1**2 - (X2 + r0) ** 2 / 2 - 2 * P2**2)
+          * np.sin((X1 + r0) * P1)
+          + np.pi**-2.5 * np.exp(-3 * (X2 + r0) ** 2 / 4 - P2**2 - (X1 + r0) ** 2 / 2 - 2 * P1**2)
+          * np.sin((X2 + r0) * P2))
+    out = torch.empty(f.shape, dtype=torch.float64, device="cuda")
+    s.theta(dev(f), out)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(host(out) - ex)) <= 1e-15
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("bf16x2", 2e-4)])
+def test_theta_reduced_precision(orc, precision, tol):
+    nx, nk = 6, 64
+    vext, v12 = I.double_well(), I.smoothed_coulomb(1.0, 1.0)
+    s, g = make(orc, nx, nk, precision=precision, vext=vext, v12=v12)
+    f = I.random_field((nx, nx, nk, nk), seed=7)
+    tb = orc.tables(g, vext, v12)
+    ref = orc.theta_periodic(g, tb["sig_ext"], tb["sig_ext"], tb["vhat12"], f, True)
+    out = torch.empty(f.shape, dtype=torch.float32, device="cuda")
+    s.theta(dev(f, torch.float32), out)
+    torch.cuda.synchronize()
+    e = eps_inf(host(out), ref)
+    print(f"theta {precision}: eps_inf={e:.3e}")
+    assert e <= tol
+
+
+# --------------------------------------------------------------------------
+# advection
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nx,nk,periodic,s", [
+    (32, 16, True, 0.01), (48, 16, True, -0.02), (24, 16, True, 0.01),   # 24: general path
+    (16, 32, True, 3.0),                                                 # > 1 cell: general path
+    (33, 16, False, 0.01), (20, 16, False, 0.05), (33, 16, False, 2.5),
+])
+@pytest.mark.parametrize("dim", [1, 2])
+def test_advect_fp64_matches_oracle(orc, nx, nk, periodic, s, dim):
+    kw = dict(periodic=periodic)
+    if not periodic:
+        kw.update(cells=2, x_min=-15.0, x_max=15.0, k_max=3.0)
+    sol, g = make(orc, nx, nk, **kw)
+    f = I.random_field((nx, nx, nk, nk), seed=11 + nx)
+    ref = orc.advect(g, dim, s, f)
+    out = torch.empty(f.shape, dtype=torch.float64, device="cuda")
+    sol.advect(dim, s, dev(f), out)
+    torch.cuda.synchronize()
+    e = eps_inf(host(out), ref)
+    print(f"advect nx={nx} per={periodic} s={s} dim={dim}: eps_inf={e:.3e}")
+    assert e <= 1e-12
+
+
+def test_advect_fp32(orc):
+    sol, g = make(orc, 32, 32, precision="fp32")
+    f = I.random_field((32, 32, 32, 32), seed=5)
+    ref = orc.advect(g, 2, 0.02, f)
+    out = torch.empty(f.shape, dtype=torch.float32, device="cuda")
+    sol.advect(2, 0.02, dev(f, torch.float32), out)
+    torch.cuda.synchronize()
+    assert eps_inf(host(out), ref) <= 2e-6
+
+
+# --------------------------------------------------------------------------
+# whole steps
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scheme", ["strang", "lawson"])
+def test_step_tiny_periodic_fp64(orc, scheme):
+    """Periodic 32^4 workload: 1 and 20 steps within 1e-12 of the oracle."""
+    w = I.tiny_periodic()
+    s, g = make(orc, w.nx, w.nk, dt=w.dt, scheme=scheme, vext=w.vext, v12=w.v12)
+    x, p, _ = s.nodes()
+    f0 = I.symmetrised_pair(x, p)
+    tb = orc.tables(g, w.vext, w.v12)
+    s.set_state(f0)
+    s.step(1)
+    e1 = eps_inf(s.get_state(), orc.step(g, f0, tb, 1, w.dt, scheme=scheme))
+    s.step(19)
+    ref = orc.step(g, f0, tb, 20, w.dt, scheme=scheme)
+    e20 = eps_inf(s.get_state(), ref)
+    print(f"step {scheme}: eps_inf 1 step {e1:.3e}, 20 steps {e20:.3e}")
+    assert e1 <= 1e-12 and e20 <= 1e-12
+    ob = s.observables()
+    ro = orc.observables(g, ref, tb["vext_x"], tb["v12_pair"])
+    for k in ("mass", "energy", "l2"):
+        assert abs(ob[k] - ro[k]) <= 1e-12 * abs(ro[k]), k
+    for k in ("n1", "n12", "f1"):
+        assert eps_inf(ob[k], ro[k]) <= 1e-12, k
+    ev, sv = orc.rho1_entropy(g, ro["f1"])
+    assert abs(ob["entropy"] - sv) <= 1e-9
+
+
+@pytest.mark.parametrize("lam,xc", [(1.0, False), (0.5, True)])
+@pytest.mark.parametrize("scheme", ["strang", "lawson"])
+def test_step_meanfield_fp64(orc, lam, xc, scheme):
+    """Hartree (lambda V12 * n_j) and Hedin-Lundqvist terms rebuilt from the
+    density inside the step, on a 16^2 x 32^2 torus."""
+    nx, nk = 16, 32
+    vext, v12 = I.cosine(0.5, 20.0), I.smoothed_coulomb(1.0, 1.0)
+    s, g = make(orc, nx, nk, dt=0.01, scheme=scheme, vext=vext, v12=v12, meanfield_lambda=lam,
+                xc=xc, xc_n0=0.05, n_scale=0.3)
+    x, p, _ = s.nodes()
+    f0 = I.mixture(x, p, seed=3, period=20.0)
+    tb = orc.tables(g, vext, v12)
+    s.set_state(f0)
+    s.step(5)
+    ref = orc.step(g, f0, tb, 5, 0.01, scheme=scheme, lam=lam, xc=xc, xc_n0=0.05, n_scale=0.3)
+    e = eps_inf(s.get_state(), ref)
+    print(f"meanfield lam={lam} xc={xc} {scheme}: {e:.3e}")
+    assert e <= 1e-12
+
+
+def test_step_box_sem_fp64(orc):
+    """Non-periodic box with the SEM single-body operator at a reduced shape
+    (33 x-nodes, 4 cells x 8 nodes), harmonic V_ext, no V12."""
+    w = I.box_sem(nx=33, cells=4, nodes=8)
+    s, g = make(orc, w.nx, w.nk, periodic=False, cells=w.cells, x_min=w.x_min, x_max=w.x_max,
+                k_max=w.k_max, dt=w.dt, vext=w.vext)
+    x, p, _ = s.nodes()
+    f0 = I.symmetrised_pair(x, p, a=(-2.0, 2.0), q=(0.0, 0.0))
+    tb = orc.tables(g, w.vext, None)
+    s.set_state(f0)
+    s.step(3)
+    ref = orc.step(g, f0, tb, 3, w.dt)
+    e = eps_inf(s.get_state(), ref)
+    print(f"box sem 3 steps: {e:.3e}")
+    assert e <= 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16x2", 1e-3)])
+def test_step_reduced_precision_error(orc, precision, tol):
+    """FP32 and split-BF16 whole steps against the FP64 oracle (20 steps of
+    the periodic 32^4 workload); the density error is reported."""
+    w = I.tiny_periodic()
+    s, g = make(orc, w.nx, w.nk, dt=w.dt, precision=precision, vext=w.vext, v12=w.v12)
+    x, p, _ = s.nodes()
+    f0 = I.symmetrised_pair(x, p)
+    tb = orc.tables(g, w.vext, w.v12)
+    s.set_state(f0)
+    s.step(20)
+    ref = orc.step(g, f0, tb, 20, w.dt)
+    e = eps_inf(s.get_state(), ref)
+    ro = orc.observables(g, ref)
+    ob = s.observables()
+    en1 = eps_inf(ob["n1"], ro["n1"])
+    en12 = eps_inf(ob["n12"], ro["n12"])
+    print(f"{precision} 20 steps: f {e:.3e}  n1 {en1:.3e}  n12 {en12:.3e}")
+    assert e <= tol and en1 <= tol and en12 <= tol
+
+
+def test_state_roundtrip_and_determinism(orc):
+    w = I.tiny_periodic()
+    s, g = make(orc, w.nx, w.nk, dt=w.dt, vext=w.vext, v12=w.v12)
+    x, p, _ = s.nodes()
+    f0 = I.symmetrised_pair(x, p)
+    s.set_state(f0)
+    assert np.array_equal(s.get_state(), f0)
+    s.step(3)
+    a = s.get_state()
+    s.set_state(f0)
+    s.step(3)
+    assert np.array_equal(s.get_state(), a)  # bitwise reproducible
+    # checkpoint / resume: 2 + (save, restore) + 1 == 3
+    s.set_state(f0)
+    s.step(2)
+    mid = s.get_state()
+    s.set_state(mid)
+    s.step(1)
+    assert np.array_equal(s.get_state(), a)
