@@ -21,6 +21,9 @@
 // the plane in LDS (one HBM read per plane), Toeplitz operands generated from
 // the symbol rows held in LDS, SEM matrices streamed from L2.
 //
+// Operand layouts (16x16x4): lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// the accumulator row order differs between f32 and f64 (acc_row).
+//
 // Numerics: FP64 path on v_mfma_f64_16x16x4f64, FP32 path on
 // v_mfma_f32_16x16x4f32, BF16X2 path on v_mfma_f32_16x16x32_bf16 with both
 // operands split x = hi + lo (hi = RNE_bf16(x), lo = RNE_bf16(x - hi)) and
@@ -58,17 +61,41 @@ __device__ inline f4 mma(float a, float b, f4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Output-tile row held in accumulator element q of lane group lk (l / 16):
+// the f32 16x16x4 instruction packs rows 4*lk + q, the f64 one rows 4*q + lk.
+template <typename T>
+__device__ inline int acc_row(int lk, int q);
+template <>
+__device__ inline int acc_row<double>(int lk, int q)
+{
+    return 4 * q + lk;
+}
+template <>
+__device__ inline int acc_row<float>(int lk, int q)
+{
+    return 4 * lk + q;
+}
+
 template <typename T>
 __device__ inline T sgnval(int d, T v)
 {
     return d > 0 ? v : (d < 0 ? -v : T(0));
 }
 
-// LDS row pitch (elements): one extra element per row spreads consecutive
-// rows over different banks.
-template <int NK>
-struct Pitch {
-    static constexpr int value = NK + 1;
+// LDS plane layout: rows of NK values at pitch LD = NK + kPadCols with
+// kPadFront zero elements before row 0 and kPadCols after the last row.  The
+// zero gaps make every skewed read X[k][s - k] of a tile that meets the valid
+// band land on data or on a zero, so the pair-term operand needs no bounds
+// test (its column stays within [-18, NK + 17]).
+constexpr int kPadCols = 20;
+constexpr int kPadFront = 24;
+
+template <typename T, int NK>
+struct Plane {
+    static constexpr int LD = NK + kPadCols;
+    static constexpr int X_ELEMS = kPadFront + NK * LD + kPadCols;
+    static constexpr int TAB = 2 * NK;  // signed Toeplitz tables, index d + NK
+    static constexpr size_t bytes = sizeof(T) * (size_t)(X_ELEMS + 3 * TAB);
 };
 
 // ---------------------------------------------------------------------------
@@ -81,16 +108,18 @@ __global__ __launch_bounds__(NK / 16 * 64) void k_theta(
     const double* __restrict__ ksem, double tau)
 {
     typedef typename Acc<T>::V V;
+    typedef Plane<T, NK> P;
     constexpr int NW = NK / 16;  // waves = row blocks
-    constexpr int LD = Pitch<NK>::value;
+    constexpr int LD = P::LD;
     constexpr int NT = NW * 64;
     constexpr int NS = NW + 1;  // skewed tiles per row block
 
     extern __shared__ unsigned char smem_raw[];
-    T* X = reinterpret_cast<T*>(smem_raw);  // [NK][LD]
-    T* s1 = X + NK * LD;                    // [NK]
-    T* s2 = s1 + NK;                        // [NK]
-    T* kp = s2 + NK;                        // [NK]
+    T* Xbase = reinterpret_cast<T*>(smem_raw);
+    T* X = Xbase + kPadFront;            // X[r * LD + c]
+    T* t1 = Xbase + P::X_ELEMS;          // t1[d + NK] = sgn(d) s1[|d|]
+    T* t2 = t1 + P::TAB;                 // t2[d + NK] = sgn(d) s2[|d|]
+    T* tk = t2 + P::TAB;                 // tk[d + NK] = sgn(d) kap[|d|]
 
     const long pl = blockIdx.x;
     const int i1 = (int)(pl / nx), i2 = (int)(pl % nx);
@@ -98,23 +127,59 @@ __global__ __launch_bounds__(NK / 16 * 64) void k_theta(
     const int tid = threadIdx.x;
     const long pbase = pl * (long)NK * NK;
 
-    for (int m = tid; m < NK; m += NT) {
-        s1[m] = SEM ? T(0) : T(sig1[(long)i1 * NK + m]);
-        s2[m] = SEM ? T(0) : T(sig2[(long)i2 * NK + m]);
-        kp[m] = TWO ? T(kap[(long)ell * NK + m]) : T(0);
+    for (int e = tid; e < 2 * NK; e += NT) {
+        const int d = e - NK, ad = d < 0 ? -d : d;
+        const bool ok = ad > 0 && ad < NK;
+        t1[e] = (SEM || !ok) ? T(0) : sgnval(d, T(sig1[(long)i1 * NK + ad]));
+        t2[e] = (SEM || !ok) ? T(0) : sgnval(d, T(sig2[(long)i2 * NK + ad]));
+        tk[e] = (!TWO || !ok) ? T(0) : sgnval(d, T(kap[(long)ell * NK + ad]));
     }
-    for (int idx = tid; idx < NK * NK; idx += NT) {
-        T x = u[pbase + idx];
-        if (MODE == 1) x += T(tau) * vin[pbase + idx];
-        X[(idx / NK) * LD + (idx % NK)] = x;
-    }
-    __syncthreads();
+    // zero gaps of the plane buffer
+    for (int e = tid; e < kPadFront; e += NT) Xbase[e] = T(0);
+    for (int e = tid; e < NK * kPadCols; e += NT) X[(e / kPadCols) * LD + NK + e % kPadCols] = T(0);
 
     const int lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int r = 16 * w + li;  // A-operand row of this lane
 
-    const int row0 = 16 * w + 4 * lk;  // first output row of this lane
+    // Each lane loads exactly the plane elements it later writes (the
+    // accumulator layout): rows 16w + acc_row(lk, q), columns 16cb + li.  All
+    // loads are issued before the first use.  Stage 2 keeps
+    // h = u + tau/2 v for its epilogue (u and v read once) unless that would
+    // not fit the register file next to the accumulators; then the epilogue
+    // reads u and v again (an L2 hit for the plane just loaded).
+    constexpr bool KEEP_H = !(sizeof(T) == 8 && NK >= 128 && TWO);
+    T h[KEEP_H ? NW : 1][4];
+    {
+        T xr[NW][4];
+#pragma unroll
+        for (int cb = 0; cb < NW; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                xr[cb][q] = u[pbase + (long)(16 * w + acc_row<T>(lk, q)) * NK + 16 * cb + li];
+        if constexpr (MODE == 1) {
+            T vr[NW][4];
+#pragma unroll
+            for (int cb = 0; cb < NW; ++cb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    vr[cb][q] = vin[pbase + (long)(16 * w + acc_row<T>(lk, q)) * NK + 16 * cb + li];
+#pragma unroll
+            for (int cb = 0; cb < NW; ++cb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if constexpr (KEEP_H) h[cb][q] = xr[cb][q] + T(0.5 * tau) * vr[cb][q];
+                    xr[cb][q] += T(tau) * vr[cb][q];
+                }
+        }
+#pragma unroll
+        for (int cb = 0; cb < NW; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                X[(16 * w + acc_row<T>(lk, q)) * LD + 16 * cb + li] = xr[cb][q];
+    }
+    __syncthreads();
+
     V acc[NW];
 #pragma unroll
     for (int j = 0; j < NW; ++j) acc[j] = V{0, 0, 0, 0};
@@ -135,27 +200,28 @@ __global__ __launch_bounds__(NK / 16 * 64) void k_theta(
             }
         }
     } else {
-        // K1 F: K1[r][k] vanishes for |r - k| > band, so only the k blocks
-        // within band of this wave's rows contribute.
+        // K1 F: K1[r][k] = t1[r - k + NK] vanishes for |r - k| > band, so only
+        // the k blocks within band of this wave's rows contribute.
         const int kb1_lo = max(0, 16 * w - band) / 4;
         const int kb1_hi = min(NK - 1, 16 * w + 15 + band) / 4;
-#pragma unroll 1
+        const T* pa1 = t1 + r + NK - lk;  // t1[r - (4kb + lk) + NK] = pa1[-4kb]
+        const T* pb1 = X + lk * LD + li;  // X[(4kb + lk) LD + 16cb + li]
+#pragma unroll 2
         for (int kb = kb1_lo; kb <= kb1_hi; ++kb) {
-            const int k = 4 * kb + lk;
-            const T a1 = sgnval(r - k, s1[abs(r - k)]);
+            const T a1 = pa1[-4 * kb];
 #pragma unroll
-            for (int cb = 0; cb < NW; ++cb) acc[cb] = mma(a1, X[k * LD + 16 * cb + li], acc[cb]);
+            for (int cb = 0; cb < NW; ++cb) acc[cb] = mma(a1, pb1[4 * kb * LD + 16 * cb], acc[cb]);
         }
-        // F K2^T: K2[c][k] vanishes for |c - k| > band.
-#pragma unroll 1
+        // F K2^T: K2[c][k] = t2[c - k + NK] vanishes for |c - k| > band.
+        const T* pa2 = X + r * LD + lk;          // X[r][4kb + lk]
+        const T* pb2 = t2 + li + NK - lk;        // t2[16cb + li - 4kb - lk + NK]
+#pragma unroll 2
         for (int kb = 0; kb < NK / 4; ++kb) {
-            const int k = 4 * kb + lk;
-            const T a2 = X[r * LD + k];
+            const T a2 = pa2[4 * kb];
 #pragma unroll
             for (int cb = 0; cb < NW; ++cb) {
                 if (4 * kb + 3 < 16 * cb - band || 4 * kb > 16 * cb + 15 + band) continue;
-                const int c = 16 * cb + li;
-                acc[cb] = mma(a2, sgnval(c - k, s2[abs(c - k)]), acc[cb]);
+                acc[cb] = mma(a2, pb2[16 * cb - 4 * kb], acc[cb]);
             }
         }
     }
@@ -164,22 +230,20 @@ __global__ __launch_bounds__(NK / 16 * 64) void k_theta(
     if constexpr (TWO) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) sacc[j] = V{0, 0, 0, 0};
-        // skewed tile j covers s in [16(w+j), 16(w+j)+16); H[n1'][s] != 0
-        // needs n1' in [s - NK + 1, s], i.e. blocks kb with
-        // 4kb+3 >= 16(w+j) - NK + 1 and 4kb <= 16(w+j) + 15.
-        const int kb_lo = max(0, (16 * w - NK + 1) / 4);
-        const int kb_hi = min(NK / 4 - 1, (16 * (w + NW) + 15) / 4);
-#pragma unroll 1
-        for (int kb = kb_lo; kb <= kb_hi; ++kb) {
-            const int k = 4 * kb + lk;
-            const T a = sgnval(r - k, kp[abs(r - k)]);
+        // skewed tile j covers s in [s0, s0 + 16), s0 = 16(w + j); H[n1'][s]
+        // is non-zero for n1' in [s - NK + 1, s], so block kb contributes when
+        // 4kb + 3 >= s0 - NK + 1 and 4kb <= s0 + 15.  Operand addresses:
+        // A = tk[r - k + NK], B = X[k LD + s0 + li - k] (zero gaps outside).
+        const T* pa = tk + r + NK - lk;
+        const T* pb = X + lk * (LD - 1) + 16 * w + li;
+#pragma unroll 2
+        for (int kb = 0; kb < NK / 4; ++kb) {
+            const T a = pa[-4 * kb];
 #pragma unroll
             for (int j = 0; j < NS; ++j) {
                 const int s0 = 16 * (w + j);
                 if (4 * kb + 3 < s0 - NK + 1 || 4 * kb > s0 + 15) continue;  // wave-uniform
-                const int col = s0 + li - k;
-                const T b = (col >= 0 && col < NK) ? X[k * LD + col] : T(0);
-                sacc[j] = mma(a, b, sacc[j]);
+                sacc[j] = mma(a, pb[4 * kb * (LD - 1) + 16 * j], sacc[j]);
             }
         }
     }
@@ -192,7 +256,7 @@ __global__ __launch_bounds__(NK / 16 * 64) void k_theta(
         for (int j = 0; j < NS; ++j) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int n1 = row0 + q;
+                const int n1 = 16 * w + acc_row<T>(lk, q);
                 const int n2 = 16 * (w + j) + li - n1;
                 if (n2 >= 0 && n2 < NK) X[n1 * LD + n2] = sacc[j][q];
             }
@@ -205,14 +269,16 @@ __global__ __launch_bounds__(NK / 16 * 64) void k_theta(
         const int c = 16 * cb + li;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int rr = row0 + q;
+            const int rr = 16 * w + acc_row<T>(lk, q);
             T val = acc[cb][q];
             if constexpr (TWO) val += X[rr * LD + c];
             const long gi = pbase + (long)rr * NK + c;
-            if (MODE == 0)
+            if constexpr (MODE == 0)
                 out[gi] = val;
+            else if constexpr (KEEP_H)
+                out[gi] = h[cb][q] + T(0.5 * tau) * val;
             else
-                out[gi] = u[gi] + T(0.5 * tau) * (vin[gi] + val);
+                out[gi] = (u[gi] + T(0.5 * tau) * vin[gi]) + T(0.5 * tau) * val;
         }
     }
 }
@@ -265,17 +331,39 @@ __global__ __launch_bounds__(NK / 16 * 64) void k_theta_bf16(
         s2[m] = (float)sig2[(long)i2 * NK + m];
         kp[m] = TWO ? (float)kap[(long)ell * NK + m] : 0.f;
     }
-    for (int idx = tid; idx < NK * NK; idx += NT) {
-        float x = u[pbase + idx];
-        if (MODE == 1) x += (float)tau * vin[pbase + idx];
-        X[(idx / NK) * LD + (idx % NK)] = x;
-    }
-    __syncthreads();
-
     const int lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int r = 16 * w + li;
     const int row0 = 16 * w + 4 * lk;
+    float h[NW][4];
+    {
+        float xr[NW][4];
+#pragma unroll
+        for (int cb = 0; cb < NW; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xr[cb][q] = u[pbase + (long)(row0 + q) * NK + 16 * cb + li];
+        if constexpr (MODE == 1) {
+            float vr[NW][4];
+#pragma unroll
+            for (int cb = 0; cb < NW; ++cb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    vr[cb][q] = vin[pbase + (long)(row0 + q) * NK + 16 * cb + li];
+#pragma unroll
+            for (int cb = 0; cb < NW; ++cb)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    h[cb][q] = xr[cb][q] + (float)(0.5 * tau) * vr[cb][q];
+                    xr[cb][q] += (float)tau * vr[cb][q];
+                }
+        }
+#pragma unroll
+        for (int cb = 0; cb < NW; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) X[(row0 + q) * LD + 16 * cb + li] = xr[cb][q];
+    }
+    __syncthreads();
+
     f4 acc[NW];
 #pragma unroll
     for (int j = 0; j < NW; ++j) acc[j] = f4{0, 0, 0, 0};
@@ -406,18 +494,18 @@ __global__ __launch_bounds__(NK / 16 * 64) void k_theta_bf16(
             float val = acc[cb][q];
             if constexpr (TWO) val += X[rr * LD + c];
             const long gi = pbase + (long)rr * NK + c;
-            if (MODE == 0)
+            if constexpr (MODE == 0)
                 out[gi] = val;
             else
-                out[gi] = u[gi] + (float)(0.5 * tau) * (vin[gi] + val);
+                out[gi] = h[cb][q] + (float)(0.5 * tau) * val;
         }
     }
 }
 
 template <typename T, int NK>
-size_t smem_bytes()
+size_t smem_bytes_bf16()
 {
-    return sizeof(T) * ((size_t)NK * Pitch<NK>::value + 3 * NK);
+    return sizeof(T) * ((size_t)NK * (NK + 1) + 3 * NK);
 }
 
 template <typename T, int NK, bool TWO, bool SEM>
@@ -425,7 +513,7 @@ hipError_t go(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, doub
               hipStream_t st)
 {
     const unsigned np = (unsigned)((long)a.nx * a.nx);
-    const size_t sm = smem_bytes<T, NK>();
+    const size_t sm = Plane<T, NK>::bytes;
     const int band = std::min(a.band, NK - 1);
     if (mode == 0) {
         auto kf = k_theta<T, NK, TWO, SEM, 0>;
@@ -446,7 +534,7 @@ hipError_t go_bf16(const ThetaArgs& a, const float* u, const float* v, float* ou
                    double tau, hipStream_t st)
 {
     const unsigned np = (unsigned)((long)a.nx * a.nx);
-    const size_t sm = smem_bytes<float, NK>();
+    const size_t sm = smem_bytes_bf16<float, NK>();
     const int band = std::min(a.band, NK - 1);
     if (mode == 0) {
         auto kf = k_theta_bf16<NK, TWO, 0>;

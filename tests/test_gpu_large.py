@@ -41,16 +41,23 @@ def test_theta_sampled_planes(orc, big):
     got = out.cpu().numpy()
     del out, fin
     rng = np.random.default_rng(1)
-    planes = sorted(set(rng.integers(0, w.nx * w.nx, 24).tolist()) | {0, w.nx * w.nx - 1, w.nx + 1})
-    worst = 0.0
+    # random planes plus corners, the diagonal (no pair term) and the bulk
+    planes = sorted(set(rng.integers(0, w.nx * w.nx, 24).tolist())
+                    | {0, w.nx * w.nx - 1, w.nx + 1, 64 * w.nx + 64, 70 * w.nx + 50})
+    err, scale = 0.0, 0.0
     for pl in planes:
         ref = orc.theta_periodic(g, tb["sig_ext"], tb["sig_ext"], tb["vhat12"], f0, True, pl, 1)
         i1, i2 = divmod(pl, w.nx)
         r, o = ref[i1, i2], got[i1, i2]
-        scale = max(np.abs(r).max(), 1e-300)
-        worst = max(worst, np.abs(o - r).max() / scale)
-    print(f"128^4 theta over {len(planes)} planes: worst plane eps_inf {worst:.3e}")
-    assert worst <= 1e-12
+        err = max(err, np.abs(o - r).max())
+        scale = max(scale, np.abs(r).max())
+    # eps_inf over the sampled planes (global maximum as in Sec. 5.1); the
+    # whole-grid maximum of |Theta f| bounds the sampled one from above
+    e = err / scale
+    print(f"128^4 theta over {len(planes)} planes: eps_inf {e:.3e} (scale {scale:.3e}, "
+          f"grid max {np.abs(got).max():.3e})")
+    assert scale > 0.1 * np.abs(got).max()
+    assert e <= 1e-12
 
 
 @pytest.mark.parametrize("dim", [1, 2])
@@ -64,7 +71,10 @@ def test_advect_sampled_lines(orc, big, dim):
     del out, fin
     nk2 = w.nk * w.nk
     worst = 0.0
-    for line0 in (0, 37 * nk2 + 5 * w.nk, 127 * nk2 + 120 * w.nk):
+    # runs of nk lines (fixed other-x index and n1, all n2) through the bulk
+    # of the packets and one at the p-box edge
+    for line0 in (64 * nk2 + 64 * w.nk, 40 * nk2 + 70 * w.nk, 100 * nk2 + 60 * w.nk,
+                  127 * nk2 + 120 * w.nk):
         ref = orc.advect(g, dim, 0.5 * w.dt, f0, line0, w.nk)
         flat_r, flat_o = ref.reshape(-1), got.reshape(-1)
         # gather the touched lines
@@ -75,8 +85,8 @@ def test_advect_sampled_lines(orc, big, dim):
             else:
                 idx = o_ * w.nx * nk2 + rem + np.arange(w.nx) * nk2
             r, o = flat_r[idx], flat_o[idx]
-            worst = max(worst, np.abs(o - r).max() / max(np.abs(f0).max(), 1e-300))
-    print(f"128^4 advect dim {dim}: worst eps_inf {worst:.3e}")
+            worst = max(worst, np.abs(o - r).max() / np.abs(f0).max())
+    print(f"128^4 advect dim {dim}: eps_inf {worst:.3e} (line max {np.abs(flat_r).max():.3e})")
     assert worst <= 1e-12
 
 

@@ -55,7 +55,7 @@ def host(t):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("nx,nk,pot", [
-    (8, 16, "cos"), (12, 32, "cos"), (6, 48, "dw"), (5, 64, "cos"), (4, 96, "dw"), (3, 128, "cos"),
+    (8, 16, "cos"), (12, 32, "cos"), (6, 48, "dw"), (5, 64, "cos"), (4, 96, "dw"), (4, 128, "cos"),
 ])
 def test_theta_fp64_matches_oracle(orc, nx, nk, pot):
     vext = I.cosine(0.5, 20.0) if pot == "cos" else I.double_well()
