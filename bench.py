@@ -105,15 +105,99 @@ def cpu_baseline(w, f0, budget_s=20.0):
             "s_per_step_extrapolated": t_step}
 
 
+def bench_ensemble(a):
+    """64 uneven periodic instances (seeds 1000..1063): one batched step of
+    the whole ensemble per 'step', FP32, against a loop over 64 single
+    contexts doing the same steps."""
+    import torch
+
+    from paper_2511_11354_amd import inputs as I
+    from paper_2511_11354_amd import wig2
+
+    prec = a.precision if a.precision != "bf16x2" else "fp32"
+    ens = I.ensemble()
+    specs = [dict(nx=w.nx, nk=w.nk, dt=w.dt) for w in ens]
+    b = wig2.Batch(specs, precision=prec)
+    singles, shared = [], []
+    one = torch.cuda.Stream()
+    for i, w in enumerate(ens):
+        b.set_potentials(i, w.vext, w.v12)
+        s = wig2.Solver(w.nx, w.nk, dt=w.dt, precision=prec)
+        s.set_potentials(w.vext, w.v12)
+        x, p, _ = s.nodes()
+        f0 = I.mixture(x, p, seed=w.extra["seed"], period=w.x_max - w.x_min)
+        b.set_state(i, f0)
+        s.set_state(f0)
+        singles.append(s)
+        s1 = wig2.Solver(w.nx, w.nk, dt=w.dt, precision=prec, stream=one.cuda_stream)
+        s1.set_potentials(w.vext, w.v12)
+        s1.set_state(f0)
+        shared.append(s1)
+    t0 = time.perf_counter()
+    b.tune(a.tune_cache)
+    t_tune = time.perf_counter() - t0
+    total = sum(w.points for w in ens)
+    b.step(max(1, a.warmup))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(a.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for s in singles:
+        s.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        for s in singles:
+            s.step(1)
+    torch.cuda.synchronize()
+    dt_loop = time.perf_counter() - t0
+    for s in shared:
+        s.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        for s in shared:
+            s.step(1)
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t0
+    sizes = {}
+    for w in ens:
+        sizes[f"{w.nx}x{w.nk}"] = sizes.get(f"{w.nx}x{w.nk}", 0) + 1
+    out = {
+        "metric": METRIC, "value": total * a.steps / dt, "unit": "point-updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": "ensemble-64-uneven", "instances": len(ens), "points": total,
+                   "sizes_nx_x_nk": sizes, "precision": prec, "dt": 0.005, "scheme": "strang"},
+        "loop_of_single_contexts": {"value": total * a.steps / dt_loop,
+                                    "ms_per_step": dt_loop / a.steps * 1e3,
+                                    "note": "one stream per context (runs concurrently)"},
+        "loop_on_one_stream": {"value": total * a.steps / dt_seq,
+                               "ms_per_step": dt_seq / a.steps * 1e3},
+        "speedup_vs_loop": dt_loop / dt,
+        "speedup_vs_one_stream_loop": dt_seq / dt,
+        "tuning": dict(b.info(), seconds=t_tune),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x2"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x2"],
+                    help="default: fp64 for the single-grid workloads, fp32 for the ensemble")
     ap.add_argument("--scheme", default="strang", choices=["strang", "lawson"])
-    ap.add_argument("--workload", default="large", choices=["large", "tiny"])
+    ap.add_argument("--workload", default="large", choices=["large", "tiny", "ensemble"])
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "profiles", "tune_cache.json"),
+                    help="autotuner cache for the ensemble workload")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run plain device copies of the state size (for counter scaling)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU slab "
@@ -127,6 +211,10 @@ def main():
     from paper_2511_11354_amd import wig2
 
     torch.cuda.set_device(0)
+    if a.workload == "ensemble":
+        a.precision = a.precision or "fp32"
+        return bench_ensemble(a)
+    a.precision = a.precision or "fp64"
     w = I.large_periodic(u=1.0) if a.workload == "large" else I.tiny_periodic()
     s = wig2.Solver(w.nx, w.nk, x_min=w.x_min, x_max=w.x_max, dt=w.dt, scheme=a.scheme,
                     precision=a.precision)
@@ -149,6 +237,16 @@ def main():
     prof = s.profile_read(reset=True)
     s.profile(False)
     ob = s.observables()
+    if a.copy_calibration:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE
+        # counters calibrate the byte counts read for the method's kernels
+        src = torch.empty(w.points * (8 if a.precision == "fp64" else 4), dtype=torch.uint8,
+                          device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     npts = w.points
     value = npts * a.steps / dt

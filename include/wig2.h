@@ -172,6 +172,48 @@ int wig2_band(const wig2_ctx* ctx);
 /* Grid nodes: x[nx], p[nk] and p-quadrature weights w[nk] (any may be NULL). */
 int wig2_nodes(const wig2_ctx* ctx, double* x, double* p, double* w);
 
+/* ------------------------------------------------------------------------
+ * Batched ensembles of uneven periodic instances.
+ * Every instance has its own grid, parameters, potentials and state; one
+ * Strang step of the whole ensemble is six launches (two half-step sweeps,
+ * the two Theta stages, two half-step sweeps); in each phase every size
+ * class (nx for sweeps, nk for Theta) is one persistent launch over a work
+ * list spanning its instances, the class launches run as parallel branches
+ * of a HIP graph captured once and replayed per step.  Restrictions (WIG2_ENOTSUP otherwise):
+ * torus, Strang, no mean field, one precision (FP64 or FP32) for all
+ * instances, nx in {16,32,48,64,96,128}, nk in {16,32,48,64,96,128},
+ * half-step displacement at most one cell.
+ * ------------------------------------------------------------------------ */
+typedef struct wig2_batch wig2_batch;
+
+/* grids[n], params[n]: per-instance grid and parameters.  hip_stream as in
+ * wig2_create.  Allocates 3 pooled state arrays (sum of instance sizes). */
+int wig2_batch_create(int32_t n, const wig2_grid* grids, const wig2_params* params,
+                      void* hip_stream, wig2_batch** out);
+/* Per instance i in [0, n): potentials (as wig2_set_potentials), FP64 host
+ * state upload / download (as wig2_set_state / wig2_get_state). */
+int wig2_batch_set_potentials(wig2_batch* b, int32_t i, wig2_fn1 v_ext, wig2_fn1 v12, void* user);
+int wig2_batch_set_state(wig2_batch* b, int32_t i, const double* f_host);
+int wig2_batch_get_state(wig2_batch* b, int32_t i, double* f_host);
+/* Advance every instance by nsteps steps.  The first call after a change of
+ * potentials or tiling runs one step directly and captures the graph. */
+int wig2_batch_step(wig2_batch* b, int64_t nsteps);
+int wig2_batch_observables(wig2_batch* b, int32_t i, wig2_obs* obs, double* n1, double* n12,
+                           double* f1);
+/* Autotuner: times the candidate tilings (sweep grid, planes per Theta
+ * workgroup for each plane size, Theta grid) on this ensemble's data and
+ * keeps the fastest.  cache_path (may be NULL): JSON file of earlier results
+ * keyed by architecture, precision and plane size; read unless force != 0,
+ * rewritten after tuning.  The state is left unchanged. */
+int wig2_batch_tune(wig2_batch* b, const char* cache_path, int32_t force);
+/* Total points and the current tiling per size class 16, 32, 48, 64, 96, 128:
+ * theta_grid[6] (by nk), advect_grid[6] (by nx), planes_per_group[6] (by nk).
+ * Any array may be NULL. */
+int wig2_batch_info(const wig2_batch* b, int64_t* total_points, int32_t* theta_grid,
+                    int32_t* advect_grid, int32_t* planes_per_group);
+void wig2_batch_destroy(wig2_batch* b);
+const char* wig2_batch_last_error(const wig2_batch* b);
+
 void wig2_destroy(wig2_ctx* ctx);
 const char* wig2_strerror(int code);
 const char* wig2_last_error(const wig2_ctx* ctx);

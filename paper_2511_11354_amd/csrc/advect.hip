@@ -61,13 +61,11 @@ __device__ inline LineMap line_map(long line, int nx, int nk, int dim)
 // Handles displacements |c| <= 1 cell (taps d in [-2, 2]).
 // ---------------------------------------------------------------------------
 template <typename T, int NX, bool PER>
-__global__ __launch_bounds__(64) void k_advect_reg(const T* __restrict__ in, T* __restrict__ out,
-                                                   int nk, int dim, long nlines, double cpp,
-                                                   const double* __restrict__ pn,
-                                                   const double* __restrict__ thomas)
+__device__ __forceinline__ void advect_line_reg(const T* __restrict__ in, T* __restrict__ out,
+                                                int nk, int dim, long line, double cpp,
+                                                const double* __restrict__ pn,
+                                                const double* __restrict__ thomas)
 {
-    const long line = (long)blockIdx.x * 64 + threadIdx.x;
-    if (line >= nlines) return;
     const LineMap lm = line_map(line, NX, nk, dim);
     const double c = cpp * pn[lm.nv];  // displacement in cells
 
@@ -155,6 +153,17 @@ __global__ __launch_bounds__(64) void k_advect_reg(const T* __restrict__ in, T* 
         }
         out[lm.base + (long)i * lm.stride] = acc;
     }
+}
+
+template <typename T, int NX, bool PER>
+__global__ __launch_bounds__(64) void k_advect_reg(const T* __restrict__ in, T* __restrict__ out,
+                                                   int nk, int dim, long nlines, double cpp,
+                                                   const double* __restrict__ pn,
+                                                   const double* __restrict__ thomas)
+{
+    const long line = (long)blockIdx.x * 64 + threadIdx.x;
+    if (line >= nlines) return;
+    advect_line_reg<T, NX, PER>(in, out, nk, dim, line, cpp, pn, thomas);
 }
 
 // ---------------------------------------------------------------------------
@@ -248,6 +257,30 @@ __global__ __launch_bounds__(64) void k_advect_any(const T* __restrict__ in, T* 
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched sweep: every wave takes 64-line items from a list spanning all
+// instances of an ensemble (grid-stride, items pre-sorted by cost).
+// ---------------------------------------------------------------------------
+template <typename T, int NX>
+__global__ __launch_bounds__(256) void k_advect_batch(const T* __restrict__ in_pool,
+                                                      T* __restrict__ out_pool,
+                                                      const BatchInst* __restrict__ insts,
+                                                      const AdvItem* __restrict__ items, int nitems,
+                                                      int dim, const double* __restrict__ p_pool)
+{
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * 4;
+    for (int it = (blockIdx.x * 256 + threadIdx.x) >> 6; it < nitems; it += nwaves) {
+        const AdvItem item = items[it];
+        const BatchInst I = insts[item.inst];
+        const long line = item.line0 + lane;
+        if (line >= (long)NX * I.nk * I.nk) continue;
+        advect_line_reg<T, NX, true>(in_pool + I.off, out_pool + I.off, I.nk, dim, line, I.cpp,
+                                     p_pool + I.p_off, nullptr);
+    }
+}
+
 template <typename T, int NX, bool PER>
 hipError_t run_reg(const T* in, T* out, int nk, int dim, long nl, double cpp, const double* p,
                    const double* th, hipStream_t st)
@@ -259,6 +292,40 @@ hipError_t run_reg(const T* in, T* out, int nk, int dim, long nl, double cpp, co
 }
 
 }  // namespace
+
+bool batch_nx_ok(int nx)
+{
+    return nx == 16 || nx == 32 || nx == 48 || nx == 64 || nx == 96 || nx == 128;
+}
+
+template <typename T>
+hipError_t launch_advect_batch(const T* in_pool, T* out_pool, const BatchInst* insts,
+                               const AdvItem* items, int nitems, int dim, const double* p_pool,
+                               int nx, int grid, hipStream_t st)
+{
+    if (nitems == 0) return hipSuccess;
+#define WIG2_ADV_BATCH(N)                                                                        \
+    case N:                                                                                      \
+        hipLaunchKernelGGL((k_advect_batch<T, N>), dim3(grid), dim3(256), 0, st, in_pool, out_pool, \
+                           insts, items, nitems, dim, p_pool);                                   \
+        return hipGetLastError();
+    switch (nx) {
+        WIG2_ADV_BATCH(16)
+        WIG2_ADV_BATCH(32)
+        WIG2_ADV_BATCH(48)
+        WIG2_ADV_BATCH(64)
+        WIG2_ADV_BATCH(96)
+        WIG2_ADV_BATCH(128)
+    default: return hipErrorInvalidValue;
+    }
+#undef WIG2_ADV_BATCH
+}
+template hipError_t launch_advect_batch<double>(const double*, double*, const BatchInst*,
+                                                const AdvItem*, int, int, const double*, int, int,
+                                                hipStream_t);
+template hipError_t launch_advect_batch<float>(const float*, float*, const BatchInst*,
+                                               const AdvItem*, int, int, const double*, int, int,
+                                               hipStream_t);
 
 bool advect_in_registers(int nx, bool periodic, double max_cells)
 {

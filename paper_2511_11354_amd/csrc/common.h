@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/wig2.h"
+#include "wig2.h"
 
 namespace wig2 {
 
@@ -102,5 +102,51 @@ struct MeanFieldArgs {
 };
 hipError_t launch_meanfield(const MeanFieldArgs& a, const double* s0, const double* s0b,
                             double tau_b, double* sig1, double* sig2, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Batched ensembles: one launch per phase walks a work list over all
+// instances (batch.hip owns the host side).
+// ---------------------------------------------------------------------------
+struct BatchInst {
+    long off;      // element offset of the instance in the state pools
+    long tab_off;  // offset of its [nx][nk] symbol tables in the table pools
+    int nx, nk;
+    int p_off;     // offset of its momentum nodes in the node pool
+    int band;
+    int two_body;
+    int pad;
+    double cpp;    // half-step displacement per unit momentum, (dt/2)/(m dx)
+    double tau;    // dt
+};
+struct AdvItem {   // 64 consecutive lines of one instance
+    int inst;
+    int pad;
+    long line0;
+};
+struct ThItem {    // np consecutive planes of one instance
+    int inst;
+    int plane0;
+    int np;
+    int pad;
+};
+// Register-resident sizes the batched sweep supports.
+bool batch_nx_ok(int nx);
+bool batch_nk_ok(int nk);
+// Largest number of planes of size nk one batched Theta workgroup holds
+// (at most 4, 1024 threads and 160 KB of LDS).
+int batch_theta_max_planes(int nk, int elem_bytes);
+size_t batch_theta_lds(int nk, int np, int elem_bytes);
+
+// One persistent launch over the items of one size class (all instances with
+// this nx for the sweep, this nk for Theta).
+template <typename T>
+hipError_t launch_advect_batch(const T* in_pool, T* out_pool, const BatchInst* insts,
+                               const AdvItem* items, int nitems, int dim, const double* p_pool,
+                               int nx, int grid, hipStream_t st);
+template <typename T>
+hipError_t launch_theta_batch(const T* u_pool, const T* v_pool, T* out_pool,
+                              const BatchInst* insts, const ThItem* items, int nitems, int mode,
+                              const double* sig_pool, const double* kap_pool, int nk, int planes,
+                              int grid, hipStream_t st);
 
 }  // namespace wig2

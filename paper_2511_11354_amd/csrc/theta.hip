@@ -87,6 +87,9 @@ __device__ inline T sgnval(int d, T v)
 // zero gaps make every skewed read X[k][s - k] of a tile that meets the valid
 // band land on data or on a zero, so the pair-term operand needs no bounds
 // test (its column stays within [-18, NK + 17]).
+#ifndef WIG2_KEEP_H_ALWAYS
+#define WIG2_KEEP_H_ALWAYS 0
+#endif
 constexpr int kPadCols = 20;
 constexpr int kPadFront = 24;
 
@@ -99,13 +102,28 @@ struct Plane {
 };
 
 // ---------------------------------------------------------------------------
-// FP64 / FP32 kernel
+// FP64 / FP32 plane body.  One group of NK/16 waves handles one plane with
+// its own LDS slice; several groups (planes) may share a workgroup.  Every
+// thread of the workgroup calls the body with the same template arguments
+// (inactive groups with active = false), so the barriers inside match.
 // ---------------------------------------------------------------------------
+template <typename T>
+struct PlaneJob {
+    const T* u;
+    const T* v;
+    T* out;
+    long pl;  // plane index i1 * nx + i2
+    int nx;
+    const double* sig1;
+    const double* sig2;
+    const double* kap;
+    const double* ksem;
+    int band;
+    double tau;
+};
+
 template <typename T, int NK, bool TWO, bool SEM, int MODE>
-__global__ __launch_bounds__(NK / 16 * 64) void k_theta(
-    const T* u, const T* __restrict__ vin, T* out, int nx, const double* __restrict__ sig1,
-    const double* __restrict__ sig2, int band, const double* __restrict__ kap,
-    const double* __restrict__ ksem, double tau)
+__device__ __forceinline__ void theta_plane(const PlaneJob<T>& J, T* smem, int tid, bool active)
 {
     typedef typename Acc<T>::V V;
     typedef Plane<T, NK> P;
@@ -114,43 +132,51 @@ __global__ __launch_bounds__(NK / 16 * 64) void k_theta(
     constexpr int NT = NW * 64;
     constexpr int NS = NW + 1;  // skewed tiles per row block
 
-    extern __shared__ unsigned char smem_raw[];
-    T* Xbase = reinterpret_cast<T*>(smem_raw);
+    const T* u = J.u;
+    const T* __restrict__ vin = J.v;
+    T* out = J.out;
+    const int nx = J.nx, band = J.band;
+    const double tau = J.tau;
+    const double* __restrict__ sig1 = J.sig1;
+    const double* __restrict__ sig2 = J.sig2;
+    const double* __restrict__ kap = J.kap;
+    const double* __restrict__ ksem = J.ksem;
+
+    T* Xbase = smem;
     T* X = Xbase + kPadFront;            // X[r * LD + c]
     T* t1 = Xbase + P::X_ELEMS;          // t1[d + NK] = sgn(d) s1[|d|]
     T* t2 = t1 + P::TAB;                 // t2[d + NK] = sgn(d) s2[|d|]
     T* tk = t2 + P::TAB;                 // tk[d + NK] = sgn(d) kap[|d|]
 
-    const long pl = blockIdx.x;
+    const long pl = J.pl;
     const int i1 = (int)(pl / nx), i2 = (int)(pl % nx);
     const int ell = (i1 - i2 + nx) % nx;
-    const int tid = threadIdx.x;
     const long pbase = pl * (long)NK * NK;
-
-    for (int e = tid; e < 2 * NK; e += NT) {
-        const int d = e - NK, ad = d < 0 ? -d : d;
-        const bool ok = ad > 0 && ad < NK;
-        t1[e] = (SEM || !ok) ? T(0) : sgnval(d, T(sig1[(long)i1 * NK + ad]));
-        t2[e] = (SEM || !ok) ? T(0) : sgnval(d, T(sig2[(long)i2 * NK + ad]));
-        tk[e] = (!TWO || !ok) ? T(0) : sgnval(d, T(kap[(long)ell * NK + ad]));
-    }
-    // zero gaps of the plane buffer
-    for (int e = tid; e < kPadFront; e += NT) Xbase[e] = T(0);
-    for (int e = tid; e < NK * kPadCols; e += NT) X[(e / kPadCols) * LD + NK + e % kPadCols] = T(0);
 
     const int lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int r = 16 * w + li;  // A-operand row of this lane
-
-    // Each lane loads exactly the plane elements it later writes (the
-    // accumulator layout): rows 16w + acc_row(lk, q), columns 16cb + li.  All
-    // loads are issued before the first use.  Stage 2 keeps
-    // h = u + tau/2 v for its epilogue (u and v read once) unless that would
-    // not fit the register file next to the accumulators; then the epilogue
-    // reads u and v again (an L2 hit for the plane just loaded).
-    constexpr bool KEEP_H = !(sizeof(T) == 8 && NK >= 128 && TWO);
+    constexpr bool KEEP_H = WIG2_KEEP_H_ALWAYS || !(sizeof(T) == 8 && NK >= 128 && TWO);
     T h[KEEP_H ? NW : 1][4];
-    {
+
+    if (active) {
+        for (int e = tid; e < 2 * NK; e += NT) {
+            const int d = e - NK, ad = d < 0 ? -d : d;
+            const bool ok = ad > 0 && ad < NK;
+            t1[e] = (SEM || !ok) ? T(0) : sgnval(d, T(sig1[(long)i1 * NK + ad]));
+            t2[e] = (SEM || !ok) ? T(0) : sgnval(d, T(sig2[(long)i2 * NK + ad]));
+            tk[e] = (!TWO || !ok) ? T(0) : sgnval(d, T(kap[(long)ell * NK + ad]));
+        }
+        // zero gaps of the plane buffer
+        for (int e = tid; e < kPadFront; e += NT) Xbase[e] = T(0);
+        for (int e = tid; e < NK * kPadCols; e += NT) X[(e / kPadCols) * LD + NK + e % kPadCols] = T(0);
+
+        // Each lane loads exactly the plane elements it later writes (the
+        // accumulator layout): rows 16w + acc_row(lk, q), columns 16cb + li.
+        // All loads are issued before the first use.  Stage 2 keeps
+        // h = u + tau/2 v for its epilogue (u and v read once) unless that
+        // would not fit the register file next to the accumulators; then the
+        // epilogue reads u and v again.
         T xr[NW][4];
 #pragma unroll
         for (int cb = 0; cb < NW; ++cb)
@@ -181,105 +207,176 @@ __global__ __launch_bounds__(NK / 16 * 64) void k_theta(
     __syncthreads();
 
     V acc[NW];
-#pragma unroll
-    for (int j = 0; j < NW; ++j) acc[j] = V{0, 0, 0, 0};
-
-    if constexpr (SEM) {
-        const double* K1 = ksem + (long)i1 * NK * NK;
-        const double* K2 = ksem + (long)i2 * NK * NK;
-#pragma unroll 1
-        for (int kb = 0; kb < NK / 4; ++kb) {
-            const int k = 4 * kb + lk;
-            const T a1 = T(K1[(long)r * NK + k]);
-            const T a2 = X[r * LD + k];
-#pragma unroll
-            for (int cb = 0; cb < NW; ++cb) {
-                const int c = 16 * cb + li;
-                acc[cb] = mma(a1, X[k * LD + c], acc[cb]);
-                acc[cb] = mma(a2, T(K2[(long)c * NK + k]), acc[cb]);
-            }
-        }
-    } else {
-        // K1 F: K1[r][k] = t1[r - k + NK] vanishes for |r - k| > band, so only
-        // the k blocks within band of this wave's rows contribute.
-        const int kb1_lo = max(0, 16 * w - band) / 4;
-        const int kb1_hi = min(NK - 1, 16 * w + 15 + band) / 4;
-        const T* pa1 = t1 + r + NK - lk;  // t1[r - (4kb + lk) + NK] = pa1[-4kb]
-        const T* pb1 = X + lk * LD + li;  // X[(4kb + lk) LD + 16cb + li]
-#pragma unroll 2
-        for (int kb = kb1_lo; kb <= kb1_hi; ++kb) {
-            const T a1 = pa1[-4 * kb];
-#pragma unroll
-            for (int cb = 0; cb < NW; ++cb) acc[cb] = mma(a1, pb1[4 * kb * LD + 16 * cb], acc[cb]);
-        }
-        // F K2^T: K2[c][k] = t2[c - k + NK] vanishes for |c - k| > band.
-        const T* pa2 = X + r * LD + lk;          // X[r][4kb + lk]
-        const T* pb2 = t2 + li + NK - lk;        // t2[16cb + li - 4kb - lk + NK]
-#pragma unroll 2
-        for (int kb = 0; kb < NK / 4; ++kb) {
-            const T a2 = pa2[4 * kb];
-#pragma unroll
-            for (int cb = 0; cb < NW; ++cb) {
-                if (4 * kb + 3 < 16 * cb - band || 4 * kb > 16 * cb + 15 + band) continue;
-                acc[cb] = mma(a2, pb2[16 * cb - 4 * kb], acc[cb]);
-            }
-        }
-    }
-
     V sacc[NS];
-    if constexpr (TWO) {
-#pragma unroll
-        for (int j = 0; j < NS; ++j) sacc[j] = V{0, 0, 0, 0};
-        // skewed tile j covers s in [s0, s0 + 16), s0 = 16(w + j); H[n1'][s]
-        // is non-zero for n1' in [s - NK + 1, s], so block kb contributes when
-        // 4kb + 3 >= s0 - NK + 1 and 4kb <= s0 + 15.  Operand addresses:
-        // A = tk[r - k + NK], B = X[k LD + s0 + li - k] (zero gaps outside).
-        const T* pa = tk + r + NK - lk;
-        const T* pb = X + lk * (LD - 1) + 16 * w + li;
-#pragma unroll 2
-        for (int kb = 0; kb < NK / 4; ++kb) {
-            const T a = pa[-4 * kb];
-#pragma unroll
-            for (int j = 0; j < NS; ++j) {
-                const int s0 = 16 * (w + j);
-                if (4 * kb + 3 < s0 - NK + 1 || 4 * kb > s0 + 15) continue;  // wave-uniform
-                sacc[j] = mma(a, pb[4 * kb * (LD - 1) + 16 * j], sacc[j]);
+    if (active) {
+    #pragma unroll
+        for (int j = 0; j < NW; ++j) acc[j] = V{0, 0, 0, 0};
+
+        if constexpr (SEM) {
+            const double* K1 = ksem + (long)i1 * NK * NK;
+            const double* K2 = ksem + (long)i2 * NK * NK;
+    #pragma unroll 1
+            for (int kb = 0; kb < NK / 4; ++kb) {
+                const int k = 4 * kb + lk;
+                const T a1 = T(K1[(long)r * NK + k]);
+                const T a2 = X[r * LD + k];
+    #pragma unroll
+                for (int cb = 0; cb < NW; ++cb) {
+                    const int c = 16 * cb + li;
+                    acc[cb] = mma(a1, X[k * LD + c], acc[cb]);
+                    acc[cb] = mma(a2, T(K2[(long)c * NK + k]), acc[cb]);
+                }
+            }
+        } else {
+            // K1 F: K1[r][k] = t1[r - k + NK] vanishes for |r - k| > band, so only
+            // the k blocks within band of this wave's rows contribute.
+            const int kb1_lo = max(0, 16 * w - band) / 4;
+            const int kb1_hi = min(NK - 1, 16 * w + 15 + band) / 4;
+            const T* pa1 = t1 + r + NK - lk;  // t1[r - (4kb + lk) + NK] = pa1[-4kb]
+            const T* pb1 = X + lk * LD + li;  // X[(4kb + lk) LD + 16cb + li]
+    #pragma unroll 2
+            for (int kb = kb1_lo; kb <= kb1_hi; ++kb) {
+                const T a1 = pa1[-4 * kb];
+    #pragma unroll
+                for (int cb = 0; cb < NW; ++cb) acc[cb] = mma(a1, pb1[4 * kb * LD + 16 * cb], acc[cb]);
+            }
+            // F K2^T: K2[c][k] = t2[c - k + NK] vanishes for |c - k| > band.
+            const T* pa2 = X + r * LD + lk;          // X[r][4kb + lk]
+            const T* pb2 = t2 + li + NK - lk;        // t2[16cb + li - 4kb - lk + NK]
+    #pragma unroll 2
+            for (int kb = 0; kb < NK / 4; ++kb) {
+                const T a2 = pa2[4 * kb];
+    #pragma unroll
+                for (int cb = 0; cb < NW; ++cb) {
+                    if (4 * kb + 3 < 16 * cb - band || 4 * kb > 16 * cb + 15 + band) continue;
+                    acc[cb] = mma(a2, pb2[16 * cb - 4 * kb], acc[cb]);
+                }
             }
         }
-    }
 
+        if constexpr (TWO) {
+    #pragma unroll
+            for (int j = 0; j < NS; ++j) sacc[j] = V{0, 0, 0, 0};
+            // skewed tile j covers s in [s0, s0 + 16), s0 = 16(w + j); H[n1'][s]
+            // is non-zero for n1' in [s - NK + 1, s], so block kb contributes when
+            // 4kb + 3 >= s0 - NK + 1 and 4kb <= s0 + 15.  Operand addresses:
+            // A = tk[r - k + NK], B = X[k LD + s0 + li - k] (zero gaps outside).
+            const T* pa = tk + r + NK - lk;
+            const T* pb = X + lk * (LD - 1) + 16 * w + li;
+    #pragma unroll 2
+            for (int kb = 0; kb < NK / 4; ++kb) {
+                const T a = pa[-4 * kb];
+    #pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    const int s0 = 16 * (w + j);
+                    if (4 * kb + 3 < s0 - NK + 1 || 4 * kb > s0 + 15) continue;  // wave-uniform
+                    sacc[j] = mma(a, pb[4 * kb * (LD - 1) + 16 * j], sacc[j]);
+                }
+            }
+        }
+
+    }
     __syncthreads();  // every wave is done reading the plane
 
     if constexpr (TWO) {
-        // scatter skewed tiles into the plane buffer: (n1, s) -> (n1, s - n1)
+        if (active) {
+            // scatter skewed tiles into the plane buffer: (n1, s) -> (n1, s - n1)
 #pragma unroll
-        for (int j = 0; j < NS; ++j) {
+            for (int j = 0; j < NS; ++j) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int n1 = 16 * w + acc_row<T>(lk, q);
-                const int n2 = 16 * (w + j) + li - n1;
-                if (n2 >= 0 && n2 < NK) X[n1 * LD + n2] = sacc[j][q];
+                for (int q = 0; q < 4; ++q) {
+                    const int n1 = 16 * w + acc_row<T>(lk, q);
+                    const int n2 = 16 * (w + j) + li - n1;
+                    if (n2 >= 0 && n2 < NK) X[n1 * LD + n2] = sacc[j][q];
+                }
             }
         }
         __syncthreads();
     }
 
+    if (active) {
 #pragma unroll
-    for (int cb = 0; cb < NW; ++cb) {
-        const int c = 16 * cb + li;
+        for (int cb = 0; cb < NW; ++cb) {
+            const int c = 16 * cb + li;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int rr = 16 * w + acc_row<T>(lk, q);
-            T val = acc[cb][q];
-            if constexpr (TWO) val += X[rr * LD + c];
-            const long gi = pbase + (long)rr * NK + c;
-            if constexpr (MODE == 0)
-                out[gi] = val;
-            else if constexpr (KEEP_H)
-                out[gi] = h[cb][q] + T(0.5 * tau) * val;
-            else
-                out[gi] = (u[gi] + T(0.5 * tau) * vin[gi]) + T(0.5 * tau) * val;
+            for (int q = 0; q < 4; ++q) {
+                const int rr = 16 * w + acc_row<T>(lk, q);
+                T val = acc[cb][q];
+                if constexpr (TWO) val += X[rr * LD + c];
+                const long gi = pbase + (long)rr * NK + c;
+                if constexpr (MODE == 0)
+                    out[gi] = val;
+                else if constexpr (KEEP_H)
+                    out[gi] = h[cb][q] + T(0.5 * tau) * val;
+                else
+                    out[gi] = (u[gi] + T(0.5 * tau) * vin[gi]) + T(0.5 * tau) * val;
+            }
         }
+    }
+    __syncthreads();  // the LDS slice may be reused by the next plane
+}
+
+// Planes per workgroup for the single-context launch: small planes share a
+// workgroup so that a workgroup has up to 8 waves.
+template <int NK>
+constexpr int planes_per_block()
+{
+    return (NK / 16 >= 8) ? 1 : (8 / (NK / 16) > 4 ? 4 : 8 / (NK / 16));
+}
+
+template <typename T, int NK, bool TWO, bool SEM, int MODE>
+__global__ __launch_bounds__(NK / 16 * 64 * planes_per_block<NK>()) void k_theta(
+    const T* u, const T* __restrict__ vin, T* out, int nx, long np, const double* __restrict__ sig1,
+    const double* __restrict__ sig2, int band, const double* __restrict__ kap,
+    const double* __restrict__ ksem, double tau)
+{
+    constexpr int NT = NK / 16 * 64;
+    extern __shared__ unsigned char smem_raw[];
+    const int g = threadIdx.x / NT;
+    const long pl = (long)blockIdx.x * planes_per_block<NK>() + g;
+    PlaneJob<T> J{u, vin, out, pl, nx, sig1, sig2, kap, ksem, band, tau};
+    T* smem = reinterpret_cast<T*>(smem_raw) + (size_t)g * (Plane<T, NK>::bytes / sizeof(T));
+    theta_plane<T, NK, TWO, SEM, MODE>(J, smem, threadIdx.x % NT, pl < np);
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched Theta: one persistent launch walks a list of (instance, planes)
+// items over the whole ensemble.  Each item is workgroup-uniform, so all its
+// waves run the same plane-size template; up to BLK/(64 NK/16) planes of the
+// item share the workgroup, one LDS slice each.
+// ---------------------------------------------------------------------------
+template <typename T, int NK, int MODE>
+__device__ __forceinline__ void theta_batch_item(const T* u_pool, const T* v_pool, T* out_pool,
+                                                 const BatchInst& I, const ThItem& item,
+                                                 const double* sig_pool, const double* kap_pool,
+                                                 T* smem)
+{
+    constexpr int NT = NK / 16 * 64;
+    const int g = threadIdx.x / NT;
+    const bool active = g < item.np;
+    PlaneJob<T> J{u_pool + I.off, v_pool ? v_pool + I.off : nullptr, out_pool + I.off,
+                  (long)item.plane0 + g, I.nx, sig_pool + I.tab_off, sig_pool + I.tab_off,
+                  kap_pool + I.tab_off, nullptr, I.band, I.tau};
+    T* slice = smem + (size_t)(active ? g : 0) * (Plane<T, NK>::bytes / sizeof(T));
+    if (I.two_body)
+        theta_plane<T, NK, true, false, MODE>(J, slice, threadIdx.x % NT, active);
+    else
+        theta_plane<T, NK, false, false, MODE>(J, slice, threadIdx.x % NT, active);
+}
+
+template <typename T, int NK, int PB, int MODE>
+__global__ __launch_bounds__(NK / 16 * 64 * PB) void k_theta_batch(
+    const T* u_pool, const T* v_pool, T* out_pool, const BatchInst* __restrict__ insts,
+    const ThItem* __restrict__ items, int nitems, const double* __restrict__ sig_pool,
+    const double* __restrict__ kap_pool)
+{
+    extern __shared__ unsigned char smem_raw[];
+    T* smem = reinterpret_cast<T*>(smem_raw);
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const ThItem item = items[it];
+        const BatchInst I = insts[item.inst];
+        theta_batch_item<T, NK, MODE>(u_pool, v_pool, out_pool, I, item, sig_pool, kap_pool, smem);
     }
 }
 
@@ -512,19 +609,22 @@ template <typename T, int NK, bool TWO, bool SEM>
 hipError_t go(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, double tau,
               hipStream_t st)
 {
-    const unsigned np = (unsigned)((long)a.nx * a.nx);
-    const size_t sm = Plane<T, NK>::bytes;
+    const long np = (long)a.nx * a.nx;
+    constexpr int PB = planes_per_block<NK>();
+    const unsigned nb = (unsigned)((np + PB - 1) / PB);
+    const size_t sm = Plane<T, NK>::bytes * PB;
     const int band = std::min(a.band, NK - 1);
+    const dim3 blk(NK / 16 * 64 * PB);
     if (mode == 0) {
         auto kf = k_theta<T, NK, TWO, SEM, 0>;
         hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-        hipLaunchKernelGGL(kf, dim3(np), dim3(NK / 16 * 64), sm, st, u, v, out, a.nx, a.sig1,
-                           a.sig2, band, a.kap, a.ksem, tau);
+        hipLaunchKernelGGL(kf, dim3(nb), blk, sm, st, u, v, out, a.nx, np, a.sig1, a.sig2, band,
+                           a.kap, a.ksem, tau);
     } else {
         auto kf = k_theta<T, NK, TWO, SEM, 1>;
         hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-        hipLaunchKernelGGL(kf, dim3(np), dim3(NK / 16 * 64), sm, st, u, v, out, a.nx, a.sig1,
-                           a.sig2, band, a.kap, a.ksem, tau);
+        hipLaunchKernelGGL(kf, dim3(nb), blk, sm, st, u, v, out, a.nx, np, a.sig1, a.sig2, band,
+                           a.kap, a.ksem, tau);
     }
     return hipGetLastError();
 }
@@ -592,6 +692,82 @@ hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int 
     default: return hipErrorNotSupported;
     }
 }
+
+
+bool batch_nk_ok(int nk) { return nk == 16 || nk == 32 || nk == 48 || nk == 64 || nk == 96 || nk == 128; }
+
+int batch_theta_max_planes(int nk, int elem_bytes)
+{
+    int p = 4;
+    while (p > 1 && (nk / 16 * 64 * p > 1024 || batch_theta_lds(nk, p, elem_bytes) > 160 * 1024)) --p;
+    return p;
+}
+
+size_t batch_theta_lds(int nk, int np, int elem_bytes)
+{
+    const size_t per = (size_t)elem_bytes * (kPadFront + (size_t)nk * (nk + kPadCols) + kPadCols + 6 * nk);
+    return per * np;
+}
+
+namespace {
+template <typename T, int NK, int PB>
+hipError_t go_batch(const T* u, const T* v, T* o, const BatchInst* insts, const ThItem* items,
+                    int nitems, int mode, const double* sig, const double* kap, int grid,
+                    hipStream_t st)
+{
+    if constexpr (NK / 16 * 64 * PB > 1024) {
+        return hipErrorInvalidValue;
+    } else {
+        const size_t lds = batch_theta_lds(NK, PB, sizeof(T));
+        if (lds > 160 * 1024) return hipErrorInvalidValue;
+        auto run = [&](auto kf) {
+            hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(kf, dim3(grid), dim3(NK / 16 * 64 * PB), lds, st, u, v, o, insts, items,
+                               nitems, sig, kap);
+            return hipGetLastError();
+        };
+        return mode == 0 ? run(k_theta_batch<T, NK, PB, 0>) : run(k_theta_batch<T, NK, PB, 1>);
+    }
+}
+template <typename T, int NK>
+hipError_t go_batch_pb(int pb, const T* u, const T* v, T* o, const BatchInst* insts, const ThItem* items,
+                       int nitems, int mode, const double* sig, const double* kap, int grid,
+                       hipStream_t st)
+{
+    switch (pb) {
+    case 1: return go_batch<T, NK, 1>(u, v, o, insts, items, nitems, mode, sig, kap, grid, st);
+    case 2: return go_batch<T, NK, 2>(u, v, o, insts, items, nitems, mode, sig, kap, grid, st);
+    case 3: return go_batch<T, NK, 3>(u, v, o, insts, items, nitems, mode, sig, kap, grid, st);
+    case 4: return go_batch<T, NK, 4>(u, v, o, insts, items, nitems, mode, sig, kap, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_theta_batch(const T* u_pool, const T* v_pool, T* out_pool,
+                              const BatchInst* insts, const ThItem* items, int nitems, int mode,
+                              const double* sig_pool, const double* kap_pool, int nk, int planes,
+                              int grid, hipStream_t st)
+{
+    if (nitems == 0) return hipSuccess;
+    switch (nk) {
+    case 16: return go_batch_pb<T, 16>(planes, u_pool, v_pool, out_pool, insts, items, nitems, mode, sig_pool, kap_pool, grid, st);
+    case 32: return go_batch_pb<T, 32>(planes, u_pool, v_pool, out_pool, insts, items, nitems, mode, sig_pool, kap_pool, grid, st);
+    case 48: return go_batch_pb<T, 48>(planes, u_pool, v_pool, out_pool, insts, items, nitems, mode, sig_pool, kap_pool, grid, st);
+    case 64: return go_batch_pb<T, 64>(planes, u_pool, v_pool, out_pool, insts, items, nitems, mode, sig_pool, kap_pool, grid, st);
+    case 96: return go_batch_pb<T, 96>(planes, u_pool, v_pool, out_pool, insts, items, nitems, mode, sig_pool, kap_pool, grid, st);
+    case 128: return go_batch_pb<T, 128>(planes, u_pool, v_pool, out_pool, insts, items, nitems, mode, sig_pool, kap_pool, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_theta_batch<double>(const double*, const double*, double*,
+                                               const BatchInst*, const ThItem*, int, int,
+                                               const double*, const double*, int, int, int,
+                                               hipStream_t);
+template hipError_t launch_theta_batch<float>(const float*, const float*, float*, const BatchInst*,
+                                              const ThItem*, int, int, const double*,
+                                              const double*, int, int, int, hipStream_t);
 
 template hipError_t launch_theta<double>(const ThetaArgs&, const double*, const double*, double*,
                                          int, double, hipStream_t);

@@ -64,6 +64,20 @@ SIGNATURES = {
     "wig2_profile": ([_vp, ctypes.c_int32], ctypes.c_int),
     "wig2_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32], ctypes.c_int),
     "wig2_band": ([_vp], ctypes.c_int),
+    "wig2_batch_create": ([ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params), _vp,
+                           ctypes.POINTER(_vp)], ctypes.c_int),
+    "wig2_batch_set_potentials": ([_vp, ctypes.c_int32, FN1, FN1, _vp], ctypes.c_int),
+    "wig2_batch_set_state": ([_vp, ctypes.c_int32, _dp], ctypes.c_int),
+    "wig2_batch_get_state": ([_vp, ctypes.c_int32, _dp], ctypes.c_int),
+    "wig2_batch_step": ([_vp, ctypes.c_int64], ctypes.c_int),
+    "wig2_batch_observables": ([_vp, ctypes.c_int32, ctypes.POINTER(Obs), _dp, _dp, _dp],
+                               ctypes.c_int),
+    "wig2_batch_tune": ([_vp, ctypes.c_char_p, ctypes.c_int32], ctypes.c_int),
+    "wig2_batch_info": ([_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+                        ctypes.c_int),
+    "wig2_batch_destroy": ([_vp], None),
+    "wig2_batch_last_error": ([_vp], ctypes.c_char_p),
     "wig2_destroy": ([_vp], None),
     "wig2_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "wig2_last_error": ([_vp], ctypes.c_char_p),
@@ -219,3 +233,89 @@ class Solver:
         w = np.zeros(self.nk)
         self._check(self._L.wig2_nodes(self._h, _ptr(x), _ptr(p), _ptr(w)), "wig2_nodes")
         return x, p, w
+
+
+class Batch:
+    """An ensemble of uneven periodic instances advanced together."""
+
+    def __init__(self, specs, *, precision="fp32", stream=None):
+        """specs: list of dicts with nx, nk and optional x_min, x_max, hbar,
+        mass, dt (Strang, torus)."""
+        self._L = lib()
+        n = len(specs)
+        G = (Grid * n)()
+        P = (Params * n)()
+        self.shapes = []
+        for i, sp in enumerate(specs):
+            G[i] = Grid(sp["nx"], sp["nk"], 1, 1, sp.get("x_min", -10.0), sp.get("x_max", 10.0), 0.0)
+            P[i] = Params(sp.get("hbar", 1.0), sp.get("mass", 1.0), sp.get("dt", 0.005), STRANG,
+                          PRECISIONS[precision], 0.0, 0, 1.0, 1.0)
+            self.shapes.append((sp["nx"], sp["nx"], sp["nk"], sp["nk"]))
+        self.n = n
+        self._cbs = {}
+        h = ctypes.c_void_p()
+        s = None if stream is None else ctypes.c_void_p(int(stream))
+        rc = self._L.wig2_batch_create(n, G, P, s, ctypes.byref(h))
+        if rc != OK:
+            raise Wig2Error(rc, f"wig2_batch_create: {self._L.wig2_strerror(rc).decode()}")
+        self._h = h
+
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = self._L.wig2_batch_last_error(self._h).decode() or self._L.wig2_strerror(rc).decode()
+            raise Wig2Error(rc, f"{what}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.wig2_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_potentials(self, i, v_ext=None, v12=None):
+        cb = lambda fn: FN1(0) if fn is None else FN1(lambda x, u: float(fn(x)))
+        a, b = cb(v_ext), cb(v12)
+        self._cbs[i] = (a, b)
+        self._check(self._L.wig2_batch_set_potentials(self._h, i, a, b, None),
+                    "wig2_batch_set_potentials")
+
+    def set_state(self, i, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == self.shapes[i]
+        self._check(self._L.wig2_batch_set_state(self._h, i, _ptr(f)), "wig2_batch_set_state")
+
+    def get_state(self, i):
+        f = np.empty(self.shapes[i], dtype=np.float64)
+        self._check(self._L.wig2_batch_get_state(self._h, i, _ptr(f)), "wig2_batch_get_state")
+        return f
+
+    def step(self, n=1):
+        self._check(self._L.wig2_batch_step(self._h, int(n)), "wig2_batch_step")
+
+    def observables(self, i):
+        o = Obs()
+        nx, nk = self.shapes[i][0], self.shapes[i][2]
+        n1, n12, f1 = np.zeros(nx), np.zeros((nx, nx)), np.zeros((nx, nk))
+        self._check(self._L.wig2_batch_observables(self._h, i, ctypes.byref(o), _ptr(n1),
+                                                   _ptr(n12), _ptr(f1)), "wig2_batch_observables")
+        return {"mass": o.mass, "energy": o.energy, "l2": o.l2, "entropy": o.entropy_vn,
+                "n1": n1, "n12": n12, "f1": f1}
+
+    def tune(self, cache_path=None, force=False):
+        p = None if cache_path is None else str(cache_path).encode()
+        self._check(self._L.wig2_batch_tune(self._h, p, int(force)), "wig2_batch_tune")
+
+    def info(self):
+        tp = ctypes.c_int64()
+        tg = (ctypes.c_int32 * 6)()
+        ag = (ctypes.c_int32 * 6)()
+        pp = (ctypes.c_int32 * 6)()
+        self._check(self._L.wig2_batch_info(self._h, ctypes.byref(tp), tg, ag, pp),
+                    "wig2_batch_info")
+        cls = (16, 32, 48, 64, 96, 128)
+        return {"points": tp.value, "theta_grid": dict(zip(cls, list(tg))),
+                "advect_grid": dict(zip(cls, list(ag))), "planes_per_group": dict(zip(cls, list(pp)))}
