@@ -46,7 +46,7 @@ def kernel_model(name, npts, elem, nk, band, precision):
     if name == "theta_stage1":
         return 2 * elem * npts, fl          # read f, write Theta f
     if name == "theta_stage2":
-        return 3 * elem * npts, fl + 4 * npts  # read u, v; write u + tau/2 (v + Theta)
+        return 3 * elem * npts, fl + 4 * npts  # read the two states, write the Heun result
     return elem * npts, 4.0 * npts
 
 

@@ -156,8 +156,8 @@ int wig2_advect(wig2_ctx* ctx, int32_t dim, double s, const void* in_dev, void* 
 enum {
     WIG2_PROF_ADVECT_X1 = 0,
     WIG2_PROF_ADVECT_X2 = 1,
-    WIG2_PROF_THETA_STAGE1 = 2, /* Theta[f]                                */
-    WIG2_PROF_THETA_STAGE2 = 3, /* u + tau/2 (v + Theta[u + tau v])        */
+    WIG2_PROF_THETA_STAGE1 = 2, /* general: Theta[f];  stream: f + tau Theta[f]   */
+    WIG2_PROF_THETA_STAGE2 = 3, /* second Heun stage (both kernels)               */
     WIG2_PROF_MEANFIELD = 4,    /* density moments + mean-field symbols     */
     WIG2_PROF_N = 5
 };
@@ -168,6 +168,25 @@ int wig2_profile_read(wig2_ctx* ctx, double* ms, int64_t* counts, int32_t reset)
  * (modes below 1e-13 of the largest are dropped), nk-1 when dense or when the
  * mean field is on.  >= 0 on success. */
 int wig2_band(const wig2_ctx* ctx);
+
+/* Theta kernel selection.  WIG2_THETA_GENERAL: one plane per workgroup,
+ * single-body products on the matrix cores over the symbol's band (any band,
+ * box SEM matrices, bf16x2).  WIG2_THETA_STREAM: persistent workgroups that
+ * prefetch the next plane while the matrix cores contract the pair term of
+ * the current one; single-body differences on the vector ALUs; needs a
+ * torus, FP64 or FP32, nk in {32, 48, 64, 96, 128} and a single-body band of
+ * at most 4 modes (e.g. V_ext = V0 cos(2 pi x / L)).  Its Heun step is
+ * g = f + dt Theta f, f' = (f + g)/2 + (dt/2) Theta g, equal to the general
+ * kernels' f + (dt/2)(Theta f + Theta g) up to rounding.
+ * WIG2_THETA_AUTO (default): the streaming kernel whenever it applies.
+ * wig2_set_theta_path returns WIG2_ENOTSUP for STREAM when the current
+ * potentials rule it out (the choice then stays unchanged); with AUTO or
+ * STREAM, potentials set later that rule it out select GENERAL.
+ * wig2_theta_path returns the kernel the next step uses (>= 0), or
+ * WIG2_ESTATE before wig2_set_potentials. */
+enum { WIG2_THETA_AUTO = 0, WIG2_THETA_GENERAL = 1, WIG2_THETA_STREAM = 2 };
+int wig2_set_theta_path(wig2_ctx* ctx, int32_t path);
+int wig2_theta_path(const wig2_ctx* ctx);
 
 /* Grid nodes: x[nx], p[nk] and p-quadrature weights w[nk] (any may be NULL). */
 int wig2_nodes(const wig2_ctx* ctx, double* x, double* p, double* w);

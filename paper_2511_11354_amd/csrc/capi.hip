@@ -32,6 +32,7 @@ struct wig2_ctx {
     double *s0_d = nullptr, *s0b_d = nullptr, *skin_d = nullptr, *s2_d = nullptr;
     double *rows_d = nullptr, *f1_d = nullptr;
     int band = 0;
+    int theta_path = WIG2_THETA_AUTO;
     bool two_body = false, meanfield = false;
     std::vector<double> x, p, w, vext_x, v12pair;
     double pmax = 0.0;
@@ -167,6 +168,11 @@ hipError_t theta(wig2_ctx* c, const T* u, const T* v, T* out, int mode, double t
     return launch_theta<T>(theta_args(c), u, v, out, mode, tau, c->st);
 }
 
+bool use_stream(wig2_ctx* c)
+{
+    return c->theta_path != WIG2_THETA_GENERAL && theta_stream_ok(theta_args(c));
+}
+
 template <typename T>
 hipError_t update_meanfield(wig2_ctx* c, const T* a, const T* b, double tau_b)
 {
@@ -204,6 +210,34 @@ hipError_t step_once(wig2_ctx* c)
     auto MF = [&](const T* a, const T* b, double tb) {
         return timed(c, WIG2_PROF_MEANFIELD, [&] { return update_meanfield<T>(c, a, b, tb); });
     };
+    auto THS = [&](const T* x, const T* y, T* out, int form) {
+        return timed(c, form == 1 ? WIG2_PROF_THETA_STAGE1 : WIG2_PROF_THETA_STAGE2,
+                     [&] { return launch_theta_stream<T>(theta_args(c), x, y, out, form, tau, c->st); });
+    };
+    if (use_stream(c)) {
+        // Heun as g = f + tau Theta f, then (f + g)/2 + (tau/2) Theta g.
+        // Lawson: A_tau g = a + tau b, so its corrector is the same second form
+        // with x = A_tau g and y = a = A_tau f.
+        if (c->prm.scheme == WIG2_STRANG) {
+            STEPCHK(ADV(1, 0.5 * tau, f, tmp));
+            STEPCHK(ADV(2, 0.5 * tau, tmp, f));
+            if (c->meanfield) STEPCHK(MF(f, nullptr, 0.0));
+            STEPCHK(THS(f, nullptr, k1, 1));
+            STEPCHK(THS(k1, f, f, 2));
+            STEPCHK(ADV(1, 0.5 * tau, f, tmp));
+            STEPCHK(ADV(2, 0.5 * tau, tmp, f));
+        } else {
+            if (c->meanfield) STEPCHK(MF(f, nullptr, 0.0));
+            STEPCHK(THS(f, nullptr, k1, 1));
+            STEPCHK(ADV(1, tau, f, tmp));
+            STEPCHK(ADV(2, tau, tmp, f));
+            STEPCHK(ADV(1, tau, k1, tmp));
+            STEPCHK(ADV(2, tau, tmp, k1));
+            if (c->meanfield) STEPCHK(MF(k1, nullptr, 0.0));
+            STEPCHK(THS(k1, f, f, 2));
+        }
+        return hipSuccess;
+    }
     if (c->prm.scheme == WIG2_STRANG) {
         STEPCHK(ADV(1, 0.5 * tau, f, tmp));
         STEPCHK(ADV(2, 0.5 * tau, tmp, f));
@@ -486,11 +520,15 @@ int wig2_theta(wig2_ctx* c, const void* in, void* out)
     if (c->elem == 8) {
         if (c->meanfield && (e = update_meanfield<double>(c, (const double*)in, nullptr, 0.0)) != hipSuccess)
             return fail(c, WIG2_EDEVICE, hipGetErrorString(e));
-        e = theta<double>(c, (const double*)in, nullptr, (double*)out, 0, c->prm.dt);
+        e = use_stream(c) ? launch_theta_stream<double>(theta_args(c), (const double*)in, nullptr,
+                                                        (double*)out, 0, c->prm.dt, c->st)
+                          : theta<double>(c, (const double*)in, nullptr, (double*)out, 0, c->prm.dt);
     } else {
         if (c->meanfield && (e = update_meanfield<float>(c, (const float*)in, nullptr, 0.0)) != hipSuccess)
             return fail(c, WIG2_EDEVICE, hipGetErrorString(e));
-        e = theta<float>(c, (const float*)in, nullptr, (float*)out, 0, c->prm.dt);
+        e = use_stream(c) ? launch_theta_stream<float>(theta_args(c), (const float*)in, nullptr,
+                                                       (float*)out, 0, c->prm.dt, c->st)
+                          : theta<float>(c, (const float*)in, nullptr, (float*)out, 0, c->prm.dt);
     }
     if (e != hipSuccess) return fail(c, e == hipErrorNotSupported ? WIG2_ENOTSUP : WIG2_EDEVICE,
                                      std::string("theta: ") + hipGetErrorString(e));
@@ -507,6 +545,23 @@ int wig2_advect(wig2_ctx* c, int32_t dim, double s, const void* in, void* out)
                                 : advect<float>(c, dim, s, (const float*)in, (float*)out);
     if (e != hipSuccess) return fail(c, WIG2_EDEVICE, std::string("advect: ") + hipGetErrorString(e));
     return WIG2_OK;
+}
+
+int wig2_set_theta_path(wig2_ctx* c, int32_t path)
+{
+    if (!c || path < WIG2_THETA_AUTO || path > WIG2_THETA_STREAM) return WIG2_EINVAL;
+    if (path == WIG2_THETA_STREAM && c->has_pot && !theta_stream_ok(theta_args(c)))
+        return fail(c, WIG2_ENOTSUP, "streaming Theta needs a torus, FP64/FP32, nk in {32,48,64,96,128} "
+                                     "and a single-body band of at most 4 modes");
+    c->theta_path = path;
+    return WIG2_OK;
+}
+
+int wig2_theta_path(const wig2_ctx* c)
+{
+    if (!c) return WIG2_EINVAL;
+    if (!c->has_pot) return WIG2_ESTATE;
+    return use_stream(const_cast<wig2_ctx*>(c)) ? WIG2_THETA_STREAM : WIG2_THETA_GENERAL;
 }
 
 int wig2_nodes(const wig2_ctx* c, double* x, double* p, double* w)

@@ -75,6 +75,17 @@ template <typename T>
 hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, double tau,
                         hipStream_t st);
 
+// Streaming Theta (theta_stream.hip) for the torus with a single-body band of
+// at most 4 modes, FP64 or FP32, nk in {32, 48, 64, 96, 128}:
+//   form 0: out = Theta[x]
+//   form 1: out = x + tau Theta[x]
+//   form 2: out = (y + x)/2 + (tau/2) Theta[x]
+// out may alias x or y.
+bool theta_stream_ok(const ThetaArgs& a);
+template <typename T>
+hipError_t launch_theta_stream(const ThetaArgs& a, const T* x, const T* y, T* out, int form,
+                               double tau, hipStream_t st);
+
 // Per-plane moments: s0 = sum w w f, skin = sum w w f (p1^2+p2^2)/2m,
 // s2 = sum w w f^2 (each [nx*nx]); rows[pl][n1] = sum_n2 w f (optional).
 template <typename T>

@@ -1,0 +1,324 @@
+// Streaming Theta kernel for the torus when the single-body symbols have a
+// narrow band (a few Fourier modes of V_ext, Sec. 3.1.1): the pair term
+// (Sec. 3.1.2, eq. two_body_FSM) is the only dense contraction and runs on
+// the matrix cores; the single-body differences run on the vector ALUs.
+//
+// One workgroup of NK/16 waves is resident per slot and walks the planes
+// p = blockIdx.x, blockIdx.x + gridDim.x, ...  While the matrix cores work on
+// plane p from LDS, the global loads of plane p + gridDim.x are in flight
+// into registers; they are written to LDS once every wave is done with p.
+// The pair-term accumulators are in skewed coordinates (n1, s = n1 + n2) and
+// every valid accumulator element is exactly one plane point, so each lane
+// finishes its points in place (single-body terms from LDS, epilogue, store)
+// without the scatter through LDS the general kernel needs.
+//
+// Epilogue forms (x: the plane the operator acts on, y: a second state):
+//   form 0: out = Theta[x]
+//   form 1: out = x + tau Theta[x]
+//   form 2: out = (y + x)/2 + (tau/2) Theta[x]
+// Heun's step f + (tau/2)(Theta f + Theta g), g = f + tau Theta f, is form 1
+// followed by form 2 with x = g, y = f, because (tau/2) Theta f = (g - f)/2.
+// out may alias x or y: plane p of x is read (into registers) one iteration
+// before plane p of out is written, and y is read by the lane that writes
+// the same element.
+#include "common.h"
+#include "mfma.h"
+
+#include <algorithm>
+
+namespace wig2 {
+namespace {
+using namespace mf;
+
+constexpr int kStreamBand = 4;  // widest single-body band done on the VALU
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    typedef double V __attribute__((ext_vector_type(2)));
+    static constexpr int N = 2;
+};
+template <>
+struct Vec16<float> {
+    typedef float V __attribute__((ext_vector_type(4)));
+    static constexpr int N = 4;
+};
+
+// LDS plane: rows -PADR .. NK+PADR-1 at pitch LD = NK + kPadCols; the
+// PADR rows above and below the plane and the kPadCols columns after each
+// row stay zero, so every read of the single-body differences (rows n1 +- m,
+// columns n2 +- m, m <= kStreamBand) and of the skewed pair operand (columns
+// -18 .. NK+17) lands on plane data or on a zero, with no bounds test.
+template <typename T, int NK>
+struct StreamLayout {
+    static constexpr int PADR = kStreamBand;
+    static constexpr int LD = NK + kPadCols;
+    static constexpr int X_ELEMS = (NK + 2 * PADR) * LD;
+    static constexpr int TAB = 2 * NK;
+    static constexpr size_t bytes = sizeof(T) * (size_t)(X_ELEMS + TAB);
+};
+
+// Waves per SIMD to budget registers for: FP32 planes of 128 fit twice in
+// LDS, so two 8-wave workgroups share a CU when a wave stays within 128 VGPRs.
+template <typename T, int NK>
+constexpr int stream_waves_per_eu()
+{
+    return (sizeof(T) == 4 && NK == 128) ? 4 : 1;
+}
+
+template <typename T, int NK, bool TWO, int FORM>
+__global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK>())) void k_theta_stream(
+    const T* x, const T* y, T* out, int nx, long np, const double* __restrict__ sig1,
+    const double* __restrict__ sig2, int band, const double* __restrict__ kap, double tau)
+{
+    typedef typename Acc<T>::V V;
+    typedef typename Vec16<T>::V VT;
+    typedef StreamLayout<T, NK> L;
+    constexpr int NW = NK / 16;
+    constexpr int NT = NW * 64;
+    constexpr int NS = NW + 1;
+    constexpr int LD = L::LD;
+    constexpr int VN = Vec16<T>::N;
+    constexpr int NV = NK * NK / (NT * VN);  // 16-byte loads per thread per plane
+    static_assert(NK * NK % (NT * VN) == 0, "plane must split into 16-byte loads");
+
+    extern __shared__ unsigned char smem_raw[];
+    T* Xbase = reinterpret_cast<T*>(smem_raw);
+    T* X = Xbase + L::PADR * LD;  // X[n1 * LD + n2]
+    T* tk = Xbase + L::X_ELEMS;   // tk[d + NK] = sgn(d) kap[|d|]
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+
+    // zero gaps once; plane writes never touch them
+    for (int e = tid; e < L::PADR * LD; e += NT) {
+        Xbase[e] = T(0);
+        X[NK * LD + e] = T(0);
+    }
+    for (int e = tid; e < NK * kPadCols; e += NT) X[(e / kPadCols) * LD + NK + e % kPadCols] = T(0);
+
+    long pl = blockIdx.x;
+    if (pl >= np) return;  // whole workgroup leaves together
+    const long stride = gridDim.x;
+
+    // registers of the plane to be written to LDS next
+    VT xr[NV];
+    T tkv = T(0);
+    auto fetch = [&](long p) {
+        const VT* src = reinterpret_cast<const VT*>(x + p * (long)NK * NK);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) xr[v] = src[tid + v * NT];
+        if constexpr (TWO) {
+            if (tid < 2 * NK) {
+                const int i1 = (int)(p / nx), i2 = (int)(p % nx);
+                const int ell = (i1 - i2 + nx) % nx;
+                const int d = tid - NK, ad = d < 0 ? -d : d;
+                tkv = (ad > 0 && ad < NK) ? sgnval(d, T(kap[(long)ell * NK + ad])) : T(0);
+            }
+        }
+    };
+    fetch(pl);
+
+    for (; pl < np; pl += stride) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int e = (tid + v * NT) * VN;
+            *reinterpret_cast<VT*>(X + (e / NK) * LD + e % NK) = xr[v];
+        }
+        if constexpr (TWO) {
+            if (tid < 2 * NK) tk[tid] = tkv;
+        }
+        __syncthreads();
+        if (pl + stride < np) fetch(pl + stride);
+
+        const int i1 = (int)(pl / nx), i2 = (int)(pl % nx);
+        const long pbase = pl * (long)NK * NK;
+
+        V sacc[NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) sacc[j] = V{0, 0, 0, 0};
+        if constexpr (TWO) {
+            // Output tile (row block w, skewed tile j) covers s in
+            // [16(w+j), 16(w+j)+16); the 16 rows k of block KB hold non-zero
+            // H[k][s] = X[k][s - k] for that tile iff 0 <= w + j - KB <= NW.
+            // A = tk[r - k + NK] (r = 16w + li), B = X[k LD + s - k] (zero gaps
+            // outside the plane).
+            const T* pa = tk + 16 * w + li + NK - lk;
+            const T* pb = X + lk * (LD - 1) + 16 * w + li;
+#pragma unroll
+            for (int KB = 0; KB < NW; ++KB) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int kb = 4 * KB + i;
+                    const T a = pa[-4 * kb];
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) {
+                        const int d = w + j - KB;
+                        if (d < 0 || d > NW) continue;  // wave-uniform
+                        sacc[j] = mma(a, pb[4 * kb * (LD - 1) + 16 * j], sacc[j]);
+                    }
+                }
+                // keep the scheduler from hoisting every operand read of
+                // the unrolled loop (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+
+        // Lane-owned points: accumulator element (j, q) is the point
+        // n1 = 16w + acc_row(lk, q), n2 = 16(w + j) + li - n1 when 0 <= n2 < NK.
+        // Reads for points outside the plane hit the zero gaps (or clamp) and
+        // their results are not stored.
+        // Position arithmetic restarts from an opaque copy of the lane id in
+        // each loop body, so the compiler cannot hoist the 4*NS per-point
+        // addresses and masks out of the loops and keep them all live.
+        auto opaque_lane = [&]() {
+            int l = lane;
+            asm volatile("" : "+v"(l));
+            return l;
+        };
+        int el = opaque_lane();
+        auto col = [&](int j, int q) {
+            return 16 * (w + j) + (el & 15) - (16 * w + acc_row<T>(el >> 4, q));
+        };
+        auto row = [&](int q) { return 16 * w + acc_row<T>(el >> 4, q); };
+        auto lds_at = [&](int j, int q) { return X + row(q) * LD + col(j, q); };
+
+        // single-body differences (modes 1..band of x_i1 along n1, of x_i2
+        // along n2), added onto the pair-term accumulators
+        for (int m = 1; m <= band; ++m) {
+            el = opaque_lane();
+            const T s1 = T(sig1[(long)i1 * NK + m]);
+            const T s2 = T(sig2[(long)i2 * NK + m]);
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const T* xp = lds_at(j, q);
+                    sacc[j][q] += s1 * (xp[-m * LD] - xp[m * LD]) + s2 * (xp[-m] - xp[m]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+
+        // epilogue and store; y (form 2) is fetched one group of tiles ahead
+        constexpr int YG = sizeof(T) == 4 ? 1 : 2;
+        constexpr int NG = (NS + YG - 1) / YG;
+        T yv[2][YG][4];
+        auto fetch_y = [&](int g, T (&dst)[YG][4]) {
+#pragma unroll
+            for (int jj = 0; jj < YG; ++jj) {
+                const int j = g * YG + jj;
+                if (j >= NS) break;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int n1 = row(q);
+                    const int c = min(max(col(j, q), 0), NK - 1);
+                    dst[jj][q] = y[pbase + (long)n1 * NK + c];
+                }
+            }
+        };
+        el = opaque_lane();
+        if constexpr (FORM == 2) fetch_y(0, yv[0]);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if constexpr (FORM == 2) {
+                if (g + 1 < NG) fetch_y(g + 1, yv[(g + 1) & 1]);
+            }
+#pragma unroll
+            for (int jj = 0; jj < YG; ++jj) {
+                const int j = g * YG + jj;
+                if (j >= NS) break;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int n1 = row(q);
+                    const int n2 = col(j, q);
+                    const T val = sacc[j][q];
+                    T o;
+                    if constexpr (FORM == 0)
+                        o = val;
+                    else if constexpr (FORM == 1)
+                        o = *lds_at(j, q) + T(tau) * val;
+                    else
+                        o = T(0.5) * (yv[g & 1][jj][q] + *lds_at(j, q)) + T(0.5 * tau) * val;
+                    if (n2 >= 0 && n2 < NK) out[pbase + (long)n1 * NK + n2] = o;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();  // LDS plane is rewritten next iteration
+    }
+}
+
+template <typename T, int NK, bool TWO, int FORM>
+hipError_t go_stream(const ThetaArgs& a, const T* x, const T* y, T* out, double tau, hipStream_t st)
+{
+    auto kf = k_theta_stream<T, NK, TWO, FORM>;
+    const size_t sm = StreamLayout<T, NK>::bytes;
+    const int nt = NK / 16 * 64;
+    hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    int dev = 0, ncu = 0, per = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kf, nt, sm)) != hipSuccess) return e;
+    const long np = (long)a.nx * a.nx;
+    const long grid = std::min<long>(np, (long)std::max(per, 1) * ncu);
+    hipLaunchKernelGGL(kf, dim3((unsigned)grid), dim3(nt), sm, st, x, y, out, a.nx, np, a.sig1,
+                       a.sig2, a.band, a.kap, tau);
+    return hipGetLastError();
+}
+
+template <typename T, int NK, bool TWO>
+hipError_t go_stream_form(const ThetaArgs& a, const T* x, const T* y, T* out, int form, double tau,
+                          hipStream_t st)
+{
+    switch (form) {
+    case 0: return go_stream<T, NK, TWO, 0>(a, x, y, out, tau, st);
+    case 1: return go_stream<T, NK, TWO, 1>(a, x, y, out, tau, st);
+    case 2: return go_stream<T, NK, TWO, 2>(a, x, y, out, tau, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int NK>
+hipError_t go_stream_nk(const ThetaArgs& a, const T* x, const T* y, T* out, int form, double tau,
+                        hipStream_t st)
+{
+    return a.kap ? go_stream_form<T, NK, true>(a, x, y, out, form, tau, st)
+                 : go_stream_form<T, NK, false>(a, x, y, out, form, tau, st);
+}
+
+}  // namespace
+
+bool theta_stream_ok(const ThetaArgs& a)
+{
+    // (FP32 at nk = 96 spills registers; the general kernel is faster there)
+    const bool nk_ok = a.nk == 32 || a.nk == 48 || a.nk == 64 || a.nk == 128 ||
+                       (a.nk == 96 && a.precision == WIG2_FP64);
+    return nk_ok && !a.ksem && a.band >= 0 && a.band <= kStreamBand &&
+           (a.precision == WIG2_FP64 || a.precision == WIG2_FP32);
+}
+
+template <typename T>
+hipError_t launch_theta_stream(const ThetaArgs& a, const T* x, const T* y, T* out, int form,
+                               double tau, hipStream_t st)
+{
+    if (!theta_stream_ok(a) || (form == 2 && !y)) return hipErrorNotSupported;
+    switch (a.nk) {
+    case 32: return go_stream_nk<T, 32>(a, x, y, out, form, tau, st);
+    case 48: return go_stream_nk<T, 48>(a, x, y, out, form, tau, st);
+    case 64: return go_stream_nk<T, 64>(a, x, y, out, form, tau, st);
+    case 96: return go_stream_nk<T, 96>(a, x, y, out, form, tau, st);
+    case 128: return go_stream_nk<T, 128>(a, x, y, out, form, tau, st);
+    default: return hipErrorNotSupported;
+    }
+}
+
+template hipError_t launch_theta_stream<double>(const ThetaArgs&, const double*, const double*,
+                                                double*, int, double, hipStream_t);
+template hipError_t launch_theta_stream<float>(const ThetaArgs&, const float*, const float*, float*,
+                                               int, double, hipStream_t);
+
+}  // namespace wig2

@@ -26,6 +26,15 @@ def cosine(v0: float, L: float):
     return lambda x: v0 * math.cos(2.0 * math.pi * x / L)
 
 
+def fourier_modes(coeffs, L: float):
+    """V(x) = sum_m a_m cos(2 pi m x / L) + b_m sin(2 pi m x / L) for
+    coeffs = [(a_1, b_1), (a_2, b_2), ...]: a lattice potential whose
+    single-body symbol has exactly len(coeffs) modes."""
+    cs = [(m + 1, float(a), float(b)) for m, (a, b) in enumerate(coeffs)]
+    return lambda x: sum(a * math.cos(2.0 * math.pi * m * x / L) + b * math.sin(2.0 * math.pi * m * x / L)
+                         for m, a, b in cs)
+
+
 def smoothed_coulomb(u: float = 1.0, eps: float = 1.0):
     """V12(r) = u / sqrt(r^2 + eps)  (Sec. 2.3, 1-D smoothed Coulomb)."""
     return lambda r: u / math.sqrt(r * r + eps)

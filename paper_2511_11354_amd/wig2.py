@@ -64,6 +64,8 @@ SIGNATURES = {
     "wig2_profile": ([_vp, ctypes.c_int32], ctypes.c_int),
     "wig2_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32], ctypes.c_int),
     "wig2_band": ([_vp], ctypes.c_int),
+    "wig2_set_theta_path": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "wig2_theta_path": ([_vp], ctypes.c_int),
     "wig2_batch_create": ([ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params), _vp,
                            ctypes.POINTER(_vp)], ctypes.c_int),
     "wig2_batch_set_potentials": ([_vp, ctypes.c_int32, FN1, FN1, _vp], ctypes.c_int),
@@ -220,6 +222,19 @@ class Solver:
         self._check(self._L.wig2_profile_read(self._h, _ptr(ms), cnt, int(reset)),
                     "wig2_profile_read")
         return {n: (float(ms[i]), int(cnt[i])) for i, n in enumerate(PROF_NAMES)}
+
+    THETA_PATHS = {"auto": 0, "general": 1, "stream": 2}
+
+    def set_theta_path(self, path: str):
+        """Theta kernel choice: "auto", "general" or "stream"."""
+        self._check(self._L.wig2_set_theta_path(self._h, self.THETA_PATHS[path]), "wig2_set_theta_path")
+
+    def theta_path(self) -> str:
+        """Kernel the next step uses ("general" or "stream")."""
+        r = self._L.wig2_theta_path(self._h)
+        if r < 0:
+            self._check(r, "wig2_theta_path")
+        return {1: "general", 2: "stream"}[r]
 
     def band(self):
         b = self._L.wig2_band(self._h)
