@@ -271,8 +271,9 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": by / avg / 1e9, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    kfile = "paper_2511_11354_amd/csrc/theta.hip" if dom.startswith("theta") else \
-        "paper_2511_11354_amd/csrc/advect.hip"
+    theta_file = "theta_stream.hip" if s.theta_path() == "stream" else "theta.hip"
+    kfile = os.path.join("paper_2511_11354_amd", "csrc",
+                         theta_file if dom.startswith("theta") else "advect.hip")
     roof["traffic"] = load_traffic(kfile, dom, w.name, a.precision)
     roof["kernel"] = dom
     roof["algorithmic_bytes_per_launch"] = by
@@ -289,7 +290,7 @@ def main():
         "dtype": DTYPE[a.precision], "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "nk": w.nk, "points": npts, "dt": w.dt,
                    "scheme": a.scheme, "precision": a.precision, "V12_U": w.extra.get("U", 1.0),
-                   "single_body_band": band, "seed": 0},
+                   "single_body_band": band, "theta_kernel": s.theta_path(), "seed": 0},
         "roofline": roof, "cpu_baseline": cpu, "kernels": kernels,
         "observables": {"mass": ob["mass"], "energy": ob["energy"], "entropy": ob["entropy"],
                         "step": ob["step"]},
