@@ -38,11 +38,12 @@ def theta_flops_per_point(nk: int, band: int) -> float:
     return 2.0 * (2.0 * m1 + m12)
 
 
-def kernel_model(name, npts, elem, nk, band, precision):
-    """Algorithmic (bytes, flops) of one launch of a kernel class."""
+def kernel_model(name, npts, elem, nk, band, precision, dense=False):
+    """Algorithmic (bytes, flops) of one launch of a kernel class.  dense: the
+    box's SEM operator, two dense nk x nk products per plane (4 nk flops/pt)."""
     if name.startswith("advect"):
         return 2 * elem * npts, 20.0 * npts
-    fl = theta_flops_per_point(nk, band) * npts
+    fl = (4.0 * nk if dense else theta_flops_per_point(nk, band)) * npts
     if name == "theta_stage1":
         return 2 * elem * npts, fl          # read f, write Theta f
     if name == "theta_stage2":
@@ -192,7 +193,11 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x2"],
                     help="default: fp64 for the single-grid workloads, fp32 for the ensemble")
     ap.add_argument("--scheme", default="strang", choices=["strang", "lawson"])
-    ap.add_argument("--workload", default="large", choices=["large", "tiny", "ensemble"])
+    ap.add_argument("--workload", default="large", choices=["large", "tiny", "ensemble", "box"],
+                    help="large: periodic 128^4 (default); tiny: periodic 32^4; ensemble: 64 "
+                         "uneven periodic instances; box: 129^2 x 256^2 SEM box")
+    ap.add_argument("--potential", default="harmonic", choices=["harmonic", "double_well"],
+                    help="V_ext of the box workload")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "profiles", "tune_cache.json"),
                     help="autotuner cache for the ensemble workload")
     ap.add_argument("--no-cpu", action="store_true")
@@ -214,14 +219,25 @@ def main():
     if a.workload == "ensemble":
         a.precision = a.precision or "fp32"
         return bench_ensemble(a)
-    a.precision = a.precision or "fp64"
-    w = I.large_periodic(u=1.0) if a.workload == "large" else I.tiny_periodic()
-    s = wig2.Solver(w.nx, w.nk, x_min=w.x_min, x_max=w.x_max, dt=w.dt, scheme=a.scheme,
-                    precision=a.precision)
+    box = a.workload == "box"
+    a.precision = a.precision or ("fp32" if box else "fp64")
+    if box:
+        w = I.box_sem(129, 16, 16, a.potential)
+        s = wig2.Solver(w.nx, w.nk, periodic=False, sem_cells=w.cells, x_min=w.x_min,
+                        x_max=w.x_max, k_max=w.k_max, dt=w.dt, scheme=a.scheme,
+                        precision=a.precision)
+    else:
+        w = I.large_periodic(u=1.0) if a.workload == "large" else I.tiny_periodic()
+        s = wig2.Solver(w.nx, w.nk, x_min=w.x_min, x_max=w.x_max, dt=w.dt, scheme=a.scheme,
+                        precision=a.precision)
     s.set_potentials(w.vext, w.v12)
     x, p, _ = s.nodes()
-    f0 = (I.mixture(x, p, seed=0, period=w.x_max - w.x_min) if a.workload == "large"
-          else I.symmetrised_pair(x, p))
+    if a.workload == "large":
+        f0 = I.mixture(x, p, seed=0, period=w.x_max - w.x_min)
+    elif box:
+        f0 = I.symmetrised_pair(x, p, a=(-2.0, 2.0), q=(0.0, 0.0))
+    else:
+        f0 = I.symmetrised_pair(x, p)
     s.set_state(f0)
     band = s.band()
 
@@ -255,13 +271,13 @@ def main():
     for name, (ms, cnt) in prof.items():
         if cnt == 0:
             continue
-        by, fl = kernel_model(name, npts, elem, w.nk, band, a.precision)
+        by, fl = kernel_model(name, npts, elem, w.nk, band, a.precision, dense=box)
         avg = ms / cnt / 1e3
         kernels[name] = {"avg_ms": ms / cnt, "launches": cnt, "GB/s": by / avg / 1e9,
                          "TFLOP/s": fl / avg / 1e12}
     dom = max(prof, key=lambda k: prof[k][0])
     ms, cnt = prof[dom]
-    by, fl = kernel_model(dom, npts, elem, w.nk, band, a.precision)
+    by, fl = kernel_model(dom, npts, elem, w.nk, band, a.precision, dense=box)
     avg = ms / cnt / 1e3
     pk_fl = PEAK["fp64" if a.precision == "fp64" else ("fp32" if a.precision == "fp32" else "bf16")]
     t_hbm = by / (PEAK["hbm_gbs"] * 1e9)
@@ -271,7 +287,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": by / avg / 1e9, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    theta_file = "theta_stream.hip" if s.theta_path() == "stream" else "theta.hip"
+    theta_file = ("theta_panel.hip" if box and w.nk == 256 else
+                  "theta_stream.hip" if s.theta_path() == "stream" else "theta.hip")
     kfile = os.path.join("paper_2511_11354_amd", "csrc",
                          theta_file if dom.startswith("theta") else "advect.hip")
     roof["traffic"] = load_traffic(kfile, dom, w.name, a.precision)

@@ -60,8 +60,9 @@ typedef double (*wig2_fn1)(double x, void* user);
 /* Grid (Sec. 3.1 torus / Sec. 3.2 box).
  *  nx        points per x-dimension.  Torus: distinct points, dx = L/nx.
  *            Box: nodes including both ends, dx = L/(nx-1).  nx >= 4.
- *  nk        points per p-dimension.  nk >= 2.  The Theta kernels need nk a
- *            multiple of 16 (other sizes: WIG2_ENOTSUP).
+ *  nk        points per p-dimension.  Supported: 16, 32, 48, 64, 96, 128;
+ *            on a box also 256 (dense SEM operator on LDS-staged panels).
+ *            Other sizes: WIG2_ENOTSUP.
  *  periodic  1: torus, p_n = (n - nk/2) hbar pi / L.
  *            0: box; nk = sem_cells * N Chebyshev-Gauss nodes on
  *               [-hbar k_max, hbar k_max].
@@ -142,7 +143,9 @@ int wig2_observables(wig2_ctx* ctx, wig2_obs* obs, double* n1, double* n12, doub
 
 /* Operator-level entry points (for verification and composition).
  *  wig2_theta: out = Theta[in] with the current potentials (mean field, if
- *    on, from the density of `in`).
+ *    on, from the density of `in`).  in == out is allowed except on a box
+ *    with nk = 256 in FP64 or BF16X2 (several workgroups share a plane
+ *    there): WIG2_EINVAL.
  *  wig2_advect: one spline sweep along x_dim (dim 1 or 2) by time s:
  *    out(x, p) = in(x_dim - s p_dim / m, p).  in != out. */
 int wig2_theta(wig2_ctx* ctx, const void* in_dev, void* out_dev);
@@ -183,8 +186,10 @@ int wig2_band(const wig2_ctx* ctx);
  * potentials rule it out (the choice then stays unchanged); with AUTO or
  * STREAM, potentials set later that rule it out select GENERAL.
  * wig2_theta_path returns the kernel the next step uses (>= 0), or
- * WIG2_ESTATE before wig2_set_potentials. */
-enum { WIG2_THETA_AUTO = 0, WIG2_THETA_GENERAL = 1, WIG2_THETA_STREAM = 2 };
+ * WIG2_ESTATE before wig2_set_potentials.  WIG2_THETA_PANEL (reported only):
+ * box contexts with nk = 256 always use the panel kernel, which stages the
+ * dense SEM products through LDS in k panels. */
+enum { WIG2_THETA_AUTO = 0, WIG2_THETA_GENERAL = 1, WIG2_THETA_STREAM = 2, WIG2_THETA_PANEL = 3 };
 int wig2_set_theta_path(wig2_ctx* ctx, int32_t path);
 int wig2_theta_path(const wig2_ctx* ctx);
 

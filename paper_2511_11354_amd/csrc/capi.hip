@@ -28,6 +28,7 @@ struct wig2_ctx {
     double *p_d = nullptr, *w_d = nullptr, *thomas_d = nullptr;
     double *sig_ext_d = nullptr, *sig1_d = nullptr, *sig2_d = nullptr, *kap_d = nullptr;
     double *ksem_d = nullptr, *v12pair_d = nullptr, *sintab_d = nullptr;
+    float* ksem_f = nullptr;  // FP32 copy of the SEM matrices (nk = 256, FP32 / BF16X2)
     double *mf_dens_d = nullptr, *mf_veff_d = nullptr;
     double *s0_d = nullptr, *s0b_d = nullptr, *skin_d = nullptr, *s2_d = nullptr;
     double *rows_d = nullptr, *f1_d = nullptr;
@@ -109,6 +110,8 @@ int upload(wig2_ctx* c, double* d, const std::vector<double>& h)
 }
 
 bool theta_nk_ok(int nk) { return nk == 16 || nk == 32 || nk == 48 || nk == 64 || nk == 96 || nk == 128; }
+// Box planes of this size take the panel Theta kernel.
+constexpr int kPanelThetaNk = 256;
 
 // ---- step building blocks -------------------------------------------------
 
@@ -159,6 +162,9 @@ ThetaArgs theta_args(wig2_ctx* c)
     a.kap = c->two_body ? c->kap_d : nullptr;
     a.ksem = c->g.periodic ? nullptr : c->ksem_d;
     a.precision = c->prm.precision;
+    a.ksem_t = nullptr;
+    if (!c->g.periodic && c->g.nk == kPanelThetaNk)
+        a.ksem_t = c->elem == 8 ? (const void*)c->ksem_d : (const void*)c->ksem_f;
     return a;
 }
 
@@ -171,6 +177,18 @@ hipError_t theta(wig2_ctx* c, const T* u, const T* v, T* out, int mode, double t
 bool use_stream(wig2_ctx* c)
 {
     return c->theta_path != WIG2_THETA_GENERAL && theta_stream_ok(theta_args(c));
+}
+
+// Single-operand Theta forms (streaming kernel or, for nk = 256 boxes, the
+// panel kernel): 0 Theta x, 1 x + tau Theta x, 2 (y + x)/2 + tau/2 Theta x.
+bool use_forms(wig2_ctx* c) { return use_stream(c) || theta_panel_ok(theta_args(c)); }
+
+template <typename T>
+hipError_t theta_form(wig2_ctx* c, const T* x, const T* y, T* out, int form, double tau)
+{
+    const ThetaArgs a = theta_args(c);
+    if (theta_panel_ok(a)) return launch_theta_panel<T>(a, x, y, out, form, tau, c->st);
+    return launch_theta_stream<T>(a, x, y, out, form, tau, c->st);
 }
 
 template <typename T>
@@ -212,9 +230,9 @@ hipError_t step_once(wig2_ctx* c)
     };
     auto THS = [&](const T* x, const T* y, T* out, int form) {
         return timed(c, form == 1 ? WIG2_PROF_THETA_STAGE1 : WIG2_PROF_THETA_STAGE2,
-                     [&] { return launch_theta_stream<T>(theta_args(c), x, y, out, form, tau, c->st); });
+                     [&] { return theta_form<T>(c, x, y, out, form, tau); });
     };
-    if (use_stream(c)) {
+    if (use_forms(c)) {
         // Heun as g = f + tau Theta f, then (f + g)/2 + (tau/2) Theta g.
         // Lawson: A_tau g = a + tau b, so its corrector is the same second form
         // with x = A_tau g and y = a = A_tau f.
@@ -308,10 +326,11 @@ int wig2_create(const wig2_grid* grid, const wig2_params* prm, void* hip_stream,
             return WIG2_EINVAL;
     }
     if (P.xc && (!isfin(P.xc_n0) || !isfin(P.n_scale))) return WIG2_EINVAL;
-    if (!theta_nk_ok(G.nk)) return WIG2_ENOTSUP;
+    const bool panel = !G.periodic && G.nk == kPanelThetaNk;
+    if (!theta_nk_ok(G.nk) && !panel) return WIG2_ENOTSUP;
     if (P.precision == WIG2_BF16X2 && G.nk % 32 != 0) return WIG2_ENOTSUP;
     if (!G.periodic && (P.meanfield_lambda != 0.0 || P.xc)) return WIG2_ENOTSUP;
-    if (!G.periodic && P.precision == WIG2_BF16X2) return WIG2_ENOTSUP;
+    if (!G.periodic && !panel && P.precision == WIG2_BF16X2) return WIG2_ENOTSUP;
 
     wig2_ctx* c = new (std::nothrow) wig2_ctx();
     if (!c) return WIG2_ENOMEM;
@@ -348,6 +367,7 @@ int wig2_create(const wig2_grid* grid, const wig2_params* prm, void* hip_stream,
         dev_alloc(c, &c->f1_d, (size_t)nx * nk))
         return bail(WIG2_ENOMEM);
     if (!G.periodic && dev_alloc(c, &c->ksem_d, (size_t)nx * nk * nk)) return bail(WIG2_ENOMEM);
+    if (panel && c->elem == 4 && dev_alloc(c, &c->ksem_f, (size_t)nx * nk * nk)) return bail(WIG2_ENOMEM);
 
     host_nodes(c->g, c->x, c->p, c->w);
     c->pmax = 0.0;
@@ -377,8 +397,9 @@ void wig2_destroy(wig2_ctx* c)
     if (!c) return;
     if (c->st) hipStreamSynchronize(c->st);
     void* bufs[] = {c->f, c->k1, c->tmp, c->work, c->p_d, c->w_d, c->thomas_d, c->sig_ext_d, c->sig1_d,
-                    c->sig2_d, c->kap_d, c->ksem_d, c->v12pair_d, c->sintab_d, c->mf_dens_d,
-                    c->mf_veff_d, c->s0_d, c->s0b_d, c->skin_d, c->s2_d, c->rows_d, c->f1_d};
+                    c->sig2_d, c->kap_d, c->ksem_d, c->ksem_f, c->v12pair_d, c->sintab_d,
+                    c->mf_dens_d, c->mf_veff_d, c->s0_d, c->s0b_d, c->skin_d, c->s2_d, c->rows_d,
+                    c->f1_d};
     for (void* b : bufs)
         if (b) hipFree(b);
     for (auto& pe : c->prof_ev) {
@@ -437,6 +458,10 @@ int wig2_set_potentials(wig2_ctx* c, wig2_fn1 v_ext, wig2_fn1 v12, void* user)
         std::vector<double> K;
         host_sem_matrix(g, c->vext_x, K);
         if (upload(c, c->ksem_d, K)) return WIG2_EDEVICE;
+        if (c->ksem_f) {
+            const std::vector<float> Kf(K.begin(), K.end());
+            HIPCHK(c, hipMemcpy(c->ksem_f, Kf.data(), Kf.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
         c->two_body = false;
         c->band = nk;
     }
@@ -516,19 +541,19 @@ int wig2_theta(wig2_ctx* c, const void* in, void* out)
 {
     if (!c || !in || !out) return WIG2_EINVAL;
     if (!c->has_pot) return fail(c, WIG2_ESTATE, "set the potentials first");
+    if (in == out && theta_panel_ok(theta_args(c)) && (c->elem == 8 || c->prm.precision == WIG2_BF16X2))
+        return fail(c, WIG2_EINVAL, "theta: in and out must differ for nk = 256 boxes in FP64 / BF16X2");
     hipError_t e;
     if (c->elem == 8) {
         if (c->meanfield && (e = update_meanfield<double>(c, (const double*)in, nullptr, 0.0)) != hipSuccess)
             return fail(c, WIG2_EDEVICE, hipGetErrorString(e));
-        e = use_stream(c) ? launch_theta_stream<double>(theta_args(c), (const double*)in, nullptr,
-                                                        (double*)out, 0, c->prm.dt, c->st)
-                          : theta<double>(c, (const double*)in, nullptr, (double*)out, 0, c->prm.dt);
+        e = use_forms(c) ? theta_form<double>(c, (const double*)in, nullptr, (double*)out, 0, c->prm.dt)
+                         : theta<double>(c, (const double*)in, nullptr, (double*)out, 0, c->prm.dt);
     } else {
         if (c->meanfield && (e = update_meanfield<float>(c, (const float*)in, nullptr, 0.0)) != hipSuccess)
             return fail(c, WIG2_EDEVICE, hipGetErrorString(e));
-        e = use_stream(c) ? launch_theta_stream<float>(theta_args(c), (const float*)in, nullptr,
-                                                       (float*)out, 0, c->prm.dt, c->st)
-                          : theta<float>(c, (const float*)in, nullptr, (float*)out, 0, c->prm.dt);
+        e = use_forms(c) ? theta_form<float>(c, (const float*)in, nullptr, (float*)out, 0, c->prm.dt)
+                         : theta<float>(c, (const float*)in, nullptr, (float*)out, 0, c->prm.dt);
     }
     if (e != hipSuccess) return fail(c, e == hipErrorNotSupported ? WIG2_ENOTSUP : WIG2_EDEVICE,
                                      std::string("theta: ") + hipGetErrorString(e));
@@ -561,7 +586,9 @@ int wig2_theta_path(const wig2_ctx* c)
 {
     if (!c) return WIG2_EINVAL;
     if (!c->has_pot) return WIG2_ESTATE;
-    return use_stream(const_cast<wig2_ctx*>(c)) ? WIG2_THETA_STREAM : WIG2_THETA_GENERAL;
+    wig2_ctx* m = const_cast<wig2_ctx*>(c);
+    if (theta_panel_ok(theta_args(m))) return WIG2_THETA_PANEL;
+    return use_stream(m) ? WIG2_THETA_STREAM : WIG2_THETA_GENERAL;
 }
 
 int wig2_nodes(const wig2_ctx* c, double* x, double* p, double* w)

@@ -70,6 +70,7 @@ struct ThetaArgs {
     const double* kap;
     const double* ksem;
     int precision;  // WIG2_FP64 / WIG2_FP32 / WIG2_BF16X2
+    const void* ksem_t;  // box, nk = 256: SEM matrices in the state's element type
 };
 template <typename T>
 hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, double tau,
@@ -85,6 +86,15 @@ bool theta_stream_ok(const ThetaArgs& a);
 template <typename T>
 hipError_t launch_theta_stream(const ThetaArgs& a, const T* x, const T* y, T* out, int form,
                                double tau, hipStream_t st);
+
+// Panel Theta (theta_panel.hip) for box planes of nk = 256 (SEM matrices
+// too large for the one-plane-in-LDS kernel), FP64, FP32 or split-BF16;
+// forms as for the streaming kernel.  x and out must not be the same array
+// for FP64 (two workgroups share a plane).
+bool theta_panel_ok(const ThetaArgs& a);
+template <typename T>
+hipError_t launch_theta_panel(const ThetaArgs& a, const T* x, const T* y, T* out, int form,
+                              double tau, hipStream_t st);
 
 // Per-plane moments: s0 = sum w w f, skin = sum w w f (p1^2+p2^2)/2m,
 // s2 = sum w w f^2 (each [nx*nx]); rows[pl][n1] = sum_n2 w f (optional).

@@ -230,11 +230,11 @@ class Solver:
         self._check(self._L.wig2_set_theta_path(self._h, self.THETA_PATHS[path]), "wig2_set_theta_path")
 
     def theta_path(self) -> str:
-        """Kernel the next step uses ("general" or "stream")."""
+        """Kernel the next step uses ("general", "stream" or "panel")."""
         r = self._L.wig2_theta_path(self._h)
         if r < 0:
             self._check(r, "wig2_theta_path")
-        return {1: "general", 2: "stream"}[r]
+        return {1: "general", 2: "stream", 3: "panel"}[r]
 
     def band(self):
         b = self._L.wig2_band(self._h)
