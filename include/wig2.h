@@ -238,6 +238,75 @@ int wig2_batch_info(const wig2_batch* b, int64_t* total_points, int32_t* theta_g
 void wig2_batch_destroy(wig2_batch* b);
 const char* wig2_batch_last_error(const wig2_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate for the pair increment over blocks of fine steps.
+ * Not part of the paper's method: an accelerator with an exact fallback.
+ * For a block of B fine steps from f_t, the exact block gives f_full and the
+ * same B steps without Theta[V12] (Sec. 3.1.2) give f_nov; the model learns
+ * Delta = f_full - f_nov as a function of f_t.  Model: per grid point an MLP
+ * (2 tanh layers of 16) on the 17 values of f_t along the anti-diagonal
+ * through the point (n1 - m, n2 + m), |m| <= 8, plus sin and cos of
+ * 2 pi (i1 - i2)/nx and the pair strength U = V12(0); 625 parameters,
+ * trained in FP32 with Adam on the GPU, applied with BF16 weights and FP32
+ * arithmetic.  Torus contexts with a pair potential, FP64 or FP32, no mean
+ * field.
+ * ------------------------------------------------------------------------ */
+typedef struct wig2_surrogate wig2_surrogate;
+typedef struct {
+    int32_t radius;  /* anti-diagonal neighbours per side: must be 8          */
+    int32_t hidden;  /* hidden units per layer: must be 16                    */
+    int32_t block;   /* fine steps per block (B), >= 1                        */
+    int32_t epochs;  /* passes over each collected block                      */
+    int32_t batch;   /* samples per Adam step, a multiple of 256              */
+    double lr;       /* Adam step size                                        */
+    uint64_t seed;   /* weight initialisation and sample order                */
+} wig2_train_cfg;
+
+/* Create an untrained model on the current device (Xavier-uniform weights
+ * from `seed`).  The input / output scales are fixed by the first collected
+ * block (1 / max|f_t| and max|Delta|). */
+int wig2_surrogate_create(const wig2_train_cfg* cfg, wig2_surrogate** out);
+void wig2_surrogate_destroy(wig2_surrogate* s);
+const char* wig2_surrogate_last_error(const wig2_surrogate* s);
+/* Run `blocks` blocks of the context's exact dynamics from its current state.
+ * For each block the pair (f_t, Delta) is formed on the device; with train
+ * != 0 the model takes epochs x (points / batch) Adam steps on it, otherwise
+ * it is only evaluated.  The context ends on the exact trajectory (its step
+ * count advances by blocks x B).  Allocates two state-sized buffers in the
+ * context on first use.  The model remembers the context's dt; contexts with
+ * another dt are rejected (WIG2_EINVAL). */
+int wig2_surrogate_collect(wig2_surrogate* s, wig2_ctx* ctx, int32_t blocks, int32_t train);
+/* Mean squared error (in units of the output scale) of the last training
+ * epoch and of the last evaluation, Adam steps taken, samples seen. */
+int wig2_surrogate_stats(const wig2_surrogate* s, double* train_loss, double* eval_loss,
+                         int64_t* updates, int64_t* samples);
+/* Parameters (FP32 master copy, 625 values: W1[16][20], b1, W2[16][16], b2,
+ * w3, b3) and scales[3] = {in_scale, out_scale, U}.  set resets Adam. */
+int wig2_surrogate_get_params(const wig2_surrogate* s, float* params, float* scales);
+int wig2_surrogate_set_params(wig2_surrogate* s, const float* params, const float* scales);
+/* Gradient of the mean squared error over all points of caller-owned device
+ * fields ft and delta (the context's element type and grid) with the FP32
+ * weights; grad[625] and the loss are written to host memory.  At most 2^22
+ * points. */
+int wig2_surrogate_grad(wig2_surrogate* s, wig2_ctx* ctx, const void* ft_dev, const void* delta_dev,
+                        float* grad, double* loss);
+/* Attach to a context: from then on wig2_step advances whole blocks of B
+ * steps as B steps without Theta[V12] plus the model's increment.  After
+ * each block the mass and energy are compared with those at the end of the
+ * last exactly computed block (at attach: the current state); if either
+ * moved by more than drift_tol (relative) the block is redone exactly (a
+ * fallback).  Every exact_check_every blocks (0: never) the block is also
+ * computed exactly, the surrogate error eps_inf is recorded and the exact
+ * result kept.  Steps left over (nsteps mod B) run exactly.  The model must
+ * outlive the attachment; detach with wig2_surrogate_detach. */
+int wig2_surrogate_attach(wig2_ctx* ctx, const wig2_surrogate* s, double drift_tol,
+                          int32_t exact_check_every);
+int wig2_surrogate_detach(wig2_ctx* ctx);
+/* Blocks advanced with the model, fallbacks, exact checks and the eps_inf
+ * of the last check (-1 if none). */
+int wig2_surrogate_report(const wig2_ctx* ctx, int64_t* blocks, int64_t* fallbacks, int64_t* checks,
+                          double* last_check_eps);
+
 void wig2_destroy(wig2_ctx* ctx);
 const char* wig2_strerror(int code);
 const char* wig2_last_error(const wig2_ctx* ctx);

@@ -47,6 +47,37 @@ struct wig2_ctx {
     std::vector<hipEvent_t> ev_pool;
     double prof_ms[WIG2_PROF_N] = {};
     int64_t prof_cnt[WIG2_PROF_N] = {};
+    // learned pair-increment surrogate (wig2_surrogate_*)
+    bool no_pair = false;            // steps leave out Theta[V12]
+    void* ft = nullptr;              // block-start state
+    void* fs = nullptr;              // second block result
+    const wig2_surrogate* sur = nullptr;
+    double sur_tol = 0.0;
+    int sur_every = 0, sur_since = 0;
+    int64_t sur_blocks = 0, sur_fallbacks = 0, sur_checks = 0;
+    double sur_last_err = -1.0;
+    bool sur_ref_ok = false;
+    double sur_mref = 0.0, sur_eref = 0.0;
+};
+
+struct wig2_surrogate {
+    int device = 0;
+    wig2_train_cfg cfg{};
+    float* params = nullptr;
+    float* mom = nullptr;
+    float* var = nullptr;
+    unsigned short* pbf = nullptr;
+    float* partial = nullptr;  // [batch / 256][kSurP]
+    float* lpart = nullptr;    // loss sums per workgroup, one epoch
+    long lpart_cap = 0;
+    float* grad = nullptr;     // [kSurP]
+    float* maxpart = nullptr;  // [2 * kMaxParts]
+    wig2::SurScales sc{1.f, 1.f, 1.f, 0.f};
+    bool scaled = false;
+    double dt = 0.0;
+    int64_t updates = 0, samples = 0;
+    double train_loss = -1.0, eval_loss = -1.0;
+    std::string err;
 };
 
 namespace {
@@ -159,7 +190,7 @@ ThetaArgs theta_args(wig2_ctx* c)
     a.sig1 = c->meanfield ? c->sig1_d : c->sig_ext_d;
     a.sig2 = c->meanfield ? c->sig2_d : c->sig_ext_d;
     a.band = c->meanfield ? c->g.nk : c->band;
-    a.kap = c->two_body ? c->kap_d : nullptr;
+    a.kap = (c->two_body && !c->no_pair) ? c->kap_d : nullptr;
     a.ksem = c->g.periodic ? nullptr : c->ksem_d;
     a.precision = c->prm.precision;
     a.ksem_t = nullptr;
@@ -276,6 +307,215 @@ hipError_t step_once(wig2_ctx* c)
     }
 #undef STEPCHK
     return hipSuccess;
+}
+
+
+// ---- surrogate blocks -------------------------------------------------------
+
+constexpr int kMaxParts = 1024;  // workgroups of the max-reduction
+
+template <typename T>
+hipError_t run_steps(wig2_ctx* c, int n, bool no_pair)
+{
+    c->no_pair = no_pair;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n && e == hipSuccess; ++k) e = step_once<T>(c);
+    c->no_pair = false;
+    return e;
+}
+
+// Mass and energy of a state (FP64 reductions, host sums as in wig2_observables).
+template <typename T>
+int scalar_obs(wig2_ctx* c, const T* f, double& mass, double& energy)
+{
+    const int nx = c->g.nx;
+    const size_t np = (size_t)nx * nx;
+    hipError_t e = moments<T>(c, f, c->s0_d, c->skin_d, nullptr, nullptr);
+    if (e != hipSuccess) return fail(c, WIG2_EDEVICE, hipGetErrorString(e));
+    std::vector<double> s0(np), sk(np);
+    HIPCHK(c, hipMemcpyAsync(s0.data(), c->s0_d, np * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(sk.data(), c->skin_d, np * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    double m = 0.0, en = 0.0;
+    for (int i1 = 0; i1 < nx; ++i1)
+        for (int i2 = 0; i2 < nx; ++i2) {
+            const size_t q = (size_t)i1 * nx + i2;
+            const double vpot = (c->vext_x.empty() ? 0.0 : c->vext_x[i1] + c->vext_x[i2]) +
+                                (c->v12pair.empty() ? 0.0 : c->v12pair[q]);
+            m += s0[q];
+            en += sk[q] + vpot * s0[q];
+        }
+    const double dx = c->g.dx();
+    mass = dx * dx * m;
+    energy = dx * dx * en;
+    return WIG2_OK;
+}
+
+// max|a - b| and max|b| (d = a - b when d != NULL), synchronising.
+template <typename T>
+int diff_max(wig2_ctx* c, float* part, const T* a, const T* b, T* d, double& dmax, double& bmax)
+{
+    const long n = c->npts;
+    const int nwg = (int)std::min<long>(kMaxParts, (n + 255) / 256);
+    HIPCHK(c, launch_diff_max<T>(a, b, d, n, part, nwg, c->st));
+    std::vector<float> h(2 * (size_t)nwg);
+    HIPCHK(c, hipMemcpyAsync(h.data(), part, h.size() * sizeof(float), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    dmax = bmax = 0.0;
+    for (int w = 0; w < nwg; ++w) {
+        dmax = std::max(dmax, (double)h[2 * w]);
+        bmax = std::max(bmax, (double)h[2 * w + 1]);
+    }
+    return WIG2_OK;
+}
+
+int ensure_sur_buffers(wig2_ctx* c)
+{
+    const size_t bytes = (size_t)c->npts * c->elem;
+    if (!c->ft) HIPCHK(c, hipMalloc(&c->ft, bytes));
+    if (!c->fs) HIPCHK(c, hipMalloc(&c->fs, bytes));
+    return WIG2_OK;
+}
+
+long coprime_stride(long n)
+{
+    static const long primes[] = {1000003, 999983, 1000033, 999979};
+    for (long q : primes)
+        if (n % q != 0) return q % n == 0 ? 1 : q % n;
+    return 1;
+}
+
+uint64_t splitmix(uint64_t x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// One pass over (ft, delta): minibatches of cfg.batch samples in a permuted
+// order; train = Adam steps, else evaluation only.  Returns the mean loss.
+template <typename T>
+int sur_pass(wig2_surrogate* s, wig2_ctx* c, const T* ft, const T* delta, bool train, uint64_t salt,
+             double& loss)
+{
+    const long n = c->npts;
+    const long nwg_all = (n + 255) / 256 + (long)((n + s->cfg.batch - 1) / s->cfg.batch);
+    if (nwg_all > s->lpart_cap) {
+        if (s->lpart) hipFree(s->lpart);
+        s->lpart = nullptr;
+        HIPCHK(c, hipMalloc(&s->lpart, nwg_all * sizeof(float)));
+        s->lpart_cap = nwg_all;
+    }
+    const long mul = coprime_stride(n);
+    const long off = (long)(splitmix(s->cfg.seed ^ salt) % (uint64_t)n);
+    long wg_used = 0;
+    for (long k0 = 0; k0 < n; k0 += s->cfg.batch) {
+        const long cnt = std::min<long>(s->cfg.batch, n - k0);
+        const int nwg = (int)((cnt + 255) / 256);
+        HIPCHK(c, launch_sur_batch<T>(ft, delta, c->g.nx, c->g.nk, n, k0, cnt, mul, off, s->sc, s->params,
+                                      s->partial, s->lpart + wg_used, train, c->st));
+        if (train) {
+            ++s->updates;
+            HIPCHK(c, launch_sur_adam(s->params, s->mom, s->var, s->pbf, s->partial, nwg, 2.0f / (float)cnt,
+                                      (float)s->cfg.lr, (int)s->updates, nullptr, c->st));
+        }
+        wg_used += nwg;
+    }
+    std::vector<float> h((size_t)wg_used);
+    HIPCHK(c, hipMemcpyAsync(h.data(), s->lpart, h.size() * sizeof(float), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    double sum = 0.0;
+    for (float v : h) sum += v;
+    loss = sum / (double)n;
+    s->samples += n;
+    return WIG2_OK;
+}
+
+template <typename T>
+int sur_collect(wig2_surrogate* s, wig2_ctx* c, int blocks, bool train)
+{
+    T* f = static_cast<T*>(c->f);
+    T* ft = static_cast<T*>(c->ft);
+    T* fs = static_cast<T*>(c->fs);
+    T* dl = static_cast<T*>(c->k1);  // Delta lives in k1 between steps
+    const size_t bytes = (size_t)c->npts * sizeof(T);
+    const int B = s->cfg.block;
+    for (int b = 0; b < blocks; ++b) {
+        HIPCHK(c, hipMemcpyAsync(ft, f, bytes, hipMemcpyDeviceToDevice, c->st));
+        HIPCHK(c, run_steps<T>(c, B, false));
+        HIPCHK(c, hipMemcpyAsync(fs, f, bytes, hipMemcpyDeviceToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(f, ft, bytes, hipMemcpyDeviceToDevice, c->st));
+        HIPCHK(c, run_steps<T>(c, B, true));
+        double dmax, bmax, fmax, dummy;
+        if (int r = diff_max<T>(c, s->maxpart, fs, f, dl, dmax, bmax)) return r;
+        if (!s->scaled) {
+            if (int r = diff_max<T>(c, s->maxpart, ft, ft, nullptr, dummy, fmax)) return r;
+            s->sc.in_scale = fmax > 0.0 ? (float)(1.0 / fmax) : 1.f;
+            s->sc.out_scale = dmax > 0.0 ? (float)dmax : 1.f;
+            s->sc.inv_out_scale = 1.f / s->sc.out_scale;
+            s->sc.u_feat = (float)(c->v12pair.empty() ? 0.0 : c->v12pair[0]);
+            s->scaled = true;
+        }
+        double loss = 0.0;
+        const int passes = train ? std::max(1, s->cfg.epochs) : 1;
+        for (int ep = 0; ep < passes; ++ep) {
+            const uint64_t salt = ((uint64_t)c->nstep << 20) ^ ((uint64_t)b << 8) ^ (uint64_t)ep;
+            if (int r = sur_pass<T>(s, c, ft, dl, train, salt, loss)) return r;
+        }
+        if (train)
+            s->train_loss = loss;
+        else
+            s->eval_loss = loss;
+        HIPCHK(c, hipMemcpyAsync(f, fs, bytes, hipMemcpyDeviceToDevice, c->st));
+        c->nstep += B;
+        c->t += B * c->prm.dt;
+    }
+    return WIG2_OK;
+}
+
+// One block with the model attached (see wig2_surrogate_attach).
+template <typename T>
+int sur_block(wig2_ctx* c)
+{
+    const wig2_surrogate* s = c->sur;
+    T* f = static_cast<T*>(c->f);
+    T* ft = static_cast<T*>(c->ft);
+    T* fs = static_cast<T*>(c->fs);
+    const size_t bytes = (size_t)c->npts * sizeof(T);
+    const int B = s->cfg.block;
+    if (!c->sur_ref_ok) {
+        if (int r = scalar_obs<T>(c, f, c->sur_mref, c->sur_eref)) return r;
+        c->sur_ref_ok = true;
+    }
+    HIPCHK(c, hipMemcpyAsync(ft, f, bytes, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(c, run_steps<T>(c, B, true));
+    HIPCHK(c, launch_sur_apply<T>(ft, f, c->g.nx, c->g.nk, s->sc, s->pbf, c->st));
+    ++c->sur_blocks;
+    ++c->sur_since;
+    double m, en;
+    if (int r = scalar_obs<T>(c, f, m, en)) return r;
+    const double drift = std::max(std::fabs(m - c->sur_mref) / std::max(std::fabs(c->sur_mref), 1e-300),
+                                  std::fabs(en - c->sur_eref) / std::max(std::fabs(c->sur_eref), 1e-300));
+    const bool bad = !(drift <= c->sur_tol);
+    const bool check = c->sur_every > 0 && c->sur_since >= c->sur_every;
+    if (bad || check) {
+        if (check) HIPCHK(c, hipMemcpyAsync(fs, f, bytes, hipMemcpyDeviceToDevice, c->st));
+        HIPCHK(c, hipMemcpyAsync(f, ft, bytes, hipMemcpyDeviceToDevice, c->st));
+        HIPCHK(c, run_steps<T>(c, B, false));
+        if (check) {
+            double dmax, fmax;
+            if (int r = diff_max<T>(c, s->maxpart, fs, f, nullptr, dmax, fmax)) return r;
+            c->sur_last_err = fmax > 0.0 ? dmax / fmax : dmax;
+            ++c->sur_checks;
+            c->sur_since = 0;
+        }
+        if (bad) ++c->sur_fallbacks;
+        if (int r = scalar_obs<T>(c, f, c->sur_mref, c->sur_eref)) return r;
+    }
+    c->nstep += B;
+    c->t += B * c->prm.dt;
+    return WIG2_OK;
 }
 
 int ensure_work(wig2_ctx* c)
@@ -399,7 +639,7 @@ void wig2_destroy(wig2_ctx* c)
     void* bufs[] = {c->f, c->k1, c->tmp, c->work, c->p_d, c->w_d, c->thomas_d, c->sig_ext_d, c->sig1_d,
                     c->sig2_d, c->kap_d, c->ksem_d, c->ksem_f, c->v12pair_d, c->sintab_d,
                     c->mf_dens_d, c->mf_veff_d, c->s0_d, c->s0b_d, c->skin_d, c->s2_d, c->rows_d,
-                    c->f1_d};
+                    c->f1_d, c->ft, c->fs};
     for (void* b : bufs)
         if (b) hipFree(b);
     for (auto& pe : c->prof_ev) {
@@ -527,6 +767,11 @@ int wig2_step(wig2_ctx* c, int64_t n)
 {
     if (!c || n < 0) return WIG2_EINVAL;
     if (!c->has_state || !c->has_pot) return fail(c, WIG2_ESTATE, "set the state and the potentials first");
+    if (c->sur) {
+        const int B = c->sur->cfg.block;
+        for (; n >= B; n -= B)
+            if (int r = c->elem == 8 ? sur_block<double>(c) : sur_block<float>(c)) return r;
+    }
     for (int64_t k = 0; k < n; ++k) {
         hipError_t e = c->elem == 8 ? step_once<double>(c) : step_once<float>(c);
         if (e != hipSuccess) return fail(c, e == hipErrorNotSupported ? WIG2_ENOTSUP : WIG2_EDEVICE,
@@ -673,7 +918,7 @@ int wig2_observables(wig2_ctx* c, wig2_obs* o, double* n1, double* n12, double* 
     o->l2 = dx * dx * l2;
     std::vector<double> occ;
     o->entropy_vn = host_entropy(c->g, hf1, occ);
-    o->fallbacks = 0;
+    o->fallbacks = (int32_t)c->sur_fallbacks;
     if (n12) std::copy(s0.begin(), s0.end(), n12);
     if (n1)
         for (int i1 = 0; i1 < nx; ++i1) {
@@ -684,6 +929,225 @@ int wig2_observables(wig2_ctx* c, wig2_obs* o, double* n1, double* n12, double* 
     if (f1) std::copy(hf1.begin(), hf1.end(), f1);
     if (!isfin(o->mass) || !isfin(o->energy) || !isfin(o->l2))
         return fail(c, WIG2_ENUMERIC, "non-finite observable");
+    return WIG2_OK;
+}
+
+// ---- learned surrogate ---------------------------------------------------------
+
+namespace {
+int sfail(wig2_surrogate* s, int code, const std::string& m)
+{
+    if (s) s->err = m;
+    return code;
+}
+unsigned short host_bf16(float v)
+{
+    unsigned u;
+    std::memcpy(&u, &v, 4);
+    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+int sur_ctx_ok(wig2_surrogate* s, wig2_ctx* c)
+{
+    if (!c->has_state || !c->has_pot) return sfail(s, WIG2_ESTATE, "context needs state and potentials");
+    if (!c->g.periodic || !c->two_body || c->meanfield)
+        return sfail(s, WIG2_ENOTSUP, "surrogate needs a torus context with a pair potential, no mean field");
+    if (c->prm.precision == WIG2_BF16X2) return sfail(s, WIG2_ENOTSUP, "surrogate needs FP64 or FP32 state");
+    if (s->dt != 0.0 && std::fabs(s->dt - c->prm.dt) > 1e-15 * s->dt)
+        return sfail(s, WIG2_EINVAL, "model was trained with another dt");
+    return WIG2_OK;
+}
+}  // namespace
+
+const char* wig2_surrogate_last_error(const wig2_surrogate* s) { return s ? s->err.c_str() : "null model"; }
+
+int wig2_surrogate_create(const wig2_train_cfg* cfg, wig2_surrogate** out)
+{
+    if (!cfg || !out) return WIG2_EINVAL;
+    *out = nullptr;
+    if (cfg->radius != kSurR || cfg->hidden != kSurH) return WIG2_ENOTSUP;
+    if (cfg->block < 1 || cfg->epochs < 0 || cfg->batch < 256 || cfg->batch % 256 || !(cfg->lr > 0.0))
+        return WIG2_EINVAL;
+    wig2_surrogate* s = new (std::nothrow) wig2_surrogate();
+    if (!s) return WIG2_ENOMEM;
+    s->cfg = *cfg;
+    hipGetDevice(&s->device);
+    const int nwg = cfg->batch / 256;
+    bool ok = hipMalloc((void**)&s->params, kSurP * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&s->mom, kSurP * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&s->var, kSurP * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&s->pbf, kSurP * sizeof(unsigned short)) == hipSuccess &&
+              hipMalloc((void**)&s->grad, kSurP * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&s->maxpart, 2 * kMaxParts * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&s->partial, (size_t)nwg * kSurP * sizeof(float)) == hipSuccess;
+    if (!ok) {
+        wig2_surrogate_destroy(s);
+        return WIG2_ENOMEM;
+    }
+    // Xavier-uniform weights, zero biases
+    std::vector<float> p(kSurP, 0.f);
+    const int D = kSurD, H = kSurH;
+    auto fill = [&](int off, int n, int fan_in, int fan_out) {
+        const double a = std::sqrt(6.0 / (fan_in + fan_out));
+        for (int j = 0; j < n; ++j) {
+            const double u = (double)(splitmix(cfg->seed * 0x100000001B3ull + (uint64_t)(off + j)) >> 11) *
+                             (1.0 / 9007199254740992.0);
+            p[(size_t)off + j] = (float)((2.0 * u - 1.0) * a);
+        }
+    };
+    fill(0, H * D, D, H);                              // W1
+    fill(H * D + H, H * H, H, H);                      // W2
+    fill(H * D + H + H * H + H, H, H, 1);              // w3
+    if (int r = wig2_surrogate_set_params(s, p.data(), nullptr)) {
+        wig2_surrogate_destroy(s);
+        return r;
+    }
+    *out = s;
+    return WIG2_OK;
+}
+
+void wig2_surrogate_destroy(wig2_surrogate* s)
+{
+    if (!s) return;
+    void* bufs[] = {s->params, s->mom, s->var, s->pbf, s->partial, s->lpart, s->grad, s->maxpart};
+    for (void* b : bufs)
+        if (b) hipFree(b);
+    delete s;
+}
+
+int wig2_surrogate_get_params(const wig2_surrogate* s, float* params, float* scales)
+{
+    if (!s) return WIG2_EINVAL;
+    if (params && hipMemcpy(params, s->params, kSurP * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return WIG2_EDEVICE;
+    if (scales) {
+        scales[0] = s->sc.in_scale;
+        scales[1] = s->sc.out_scale;
+        scales[2] = s->sc.u_feat;
+    }
+    return WIG2_OK;
+}
+
+int wig2_surrogate_set_params(wig2_surrogate* s, const float* params, const float* scales)
+{
+    if (!s) return WIG2_EINVAL;
+    if (params) {
+        std::vector<unsigned short> b(kSurP);
+        for (int j = 0; j < kSurP; ++j) {
+            if (!std::isfinite(params[j])) return sfail(s, WIG2_EINVAL, "non-finite parameter");
+            b[j] = host_bf16(params[j]);
+        }
+        const std::vector<float> z(kSurP, 0.f);
+        if (hipMemcpy(s->params, params, kSurP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(s->pbf, b.data(), kSurP * sizeof(unsigned short), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(s->mom, z.data(), kSurP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(s->var, z.data(), kSurP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+            return sfail(s, WIG2_EDEVICE, "parameter upload failed");
+        s->updates = 0;
+    }
+    if (scales) {
+        if (!(scales[0] > 0.f) || !(scales[1] > 0.f) || !std::isfinite(scales[2]))
+            return sfail(s, WIG2_EINVAL, "scales must be positive (in, out) and finite (U)");
+        s->sc.in_scale = scales[0];
+        s->sc.out_scale = scales[1];
+        s->sc.inv_out_scale = 1.f / scales[1];
+        s->sc.u_feat = scales[2];
+        s->scaled = true;
+    }
+    return WIG2_OK;
+}
+
+int wig2_surrogate_stats(const wig2_surrogate* s, double* train_loss, double* eval_loss, int64_t* updates,
+                         int64_t* samples)
+{
+    if (!s) return WIG2_EINVAL;
+    if (train_loss) *train_loss = s->train_loss;
+    if (eval_loss) *eval_loss = s->eval_loss;
+    if (updates) *updates = s->updates;
+    if (samples) *samples = s->samples;
+    return WIG2_OK;
+}
+
+int wig2_surrogate_collect(wig2_surrogate* s, wig2_ctx* c, int32_t blocks, int32_t train)
+{
+    if (!s || !c || blocks < 0) return WIG2_EINVAL;
+    if (int r = sur_ctx_ok(s, c)) return r;
+    if (c->sur) return sfail(s, WIG2_ESTATE, "detach the model from the context first");
+    if (int r = ensure_sur_buffers(c)) return sfail(s, r, c->err);
+    if (s->dt == 0.0) s->dt = c->prm.dt;
+    const int r = c->elem == 8 ? sur_collect<double>(s, c, blocks, train != 0)
+                               : sur_collect<float>(s, c, blocks, train != 0);
+    return r ? sfail(s, r, c->err) : WIG2_OK;
+}
+
+int wig2_surrogate_grad(wig2_surrogate* s, wig2_ctx* c, const void* ft, const void* delta, float* grad,
+                        double* loss)
+{
+    if (!s || !c || !ft || !delta || !grad) return WIG2_EINVAL;
+    const long n = c->npts;
+    if (n > (1l << 22)) return sfail(s, WIG2_EINVAL, "gradient check limited to 2^22 points");
+    const int nwg = (int)((n + 255) / 256);
+    float* part = nullptr;
+    float* lp = nullptr;
+    if (hipMalloc((void**)&part, (size_t)nwg * kSurP * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&lp, (size_t)nwg * sizeof(float)) != hipSuccess) {
+        if (part) hipFree(part);
+        return WIG2_ENOMEM;
+    }
+    hipError_t e = c->elem == 8
+                       ? launch_sur_batch<double>((const double*)ft, (const double*)delta, c->g.nx, c->g.nk, n, 0,
+                                                  n, 1, 0, s->sc, s->params, part, lp, true, c->st)
+                       : launch_sur_batch<float>((const float*)ft, (const float*)delta, c->g.nx, c->g.nk, n, 0, n,
+                                                 1, 0, s->sc, s->params, part, lp, true, c->st);
+    if (e == hipSuccess)
+        e = launch_sur_adam(s->params, s->mom, s->var, s->pbf, part, nwg, 2.0f / (float)n, 0.f, 1, s->grad,
+                            c->st);
+    std::vector<float> hl((size_t)nwg);
+    if (e == hipSuccess) e = hipMemcpyAsync(grad, s->grad, kSurP * sizeof(float), hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hl.data(), lp, hl.size() * sizeof(float), hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    hipFree(part);
+    hipFree(lp);
+    if (e != hipSuccess) return sfail(s, WIG2_EDEVICE, hipGetErrorString(e));
+    if (loss) {
+        double sum = 0.0;
+        for (float v : hl) sum += v;
+        *loss = sum / (double)n;
+    }
+    return WIG2_OK;
+}
+
+int wig2_surrogate_attach(wig2_ctx* c, const wig2_surrogate* s, double drift_tol, int32_t every)
+{
+    if (!c || !s || !(drift_tol >= 0.0) || every < 0) return WIG2_EINVAL;
+    wig2_surrogate* ms = const_cast<wig2_surrogate*>(s);
+    if (int r = sur_ctx_ok(ms, c)) return fail(c, r, s->err);
+    if (!s->scaled) return fail(c, WIG2_ESTATE, "the model has no scales yet (collect or set them first)");
+    if (int r = ensure_sur_buffers(c)) return r;
+    c->sur = s;
+    c->sur_tol = drift_tol;
+    c->sur_every = every;
+    c->sur_since = 0;
+    c->sur_blocks = c->sur_fallbacks = c->sur_checks = 0;
+    c->sur_last_err = -1.0;
+    c->sur_ref_ok = false;
+    return WIG2_OK;
+}
+
+int wig2_surrogate_detach(wig2_ctx* c)
+{
+    if (!c) return WIG2_EINVAL;
+    c->sur = nullptr;
+    return WIG2_OK;
+}
+
+int wig2_surrogate_report(const wig2_ctx* c, int64_t* blocks, int64_t* fallbacks, int64_t* checks,
+                          double* last_check_eps)
+{
+    if (!c) return WIG2_EINVAL;
+    if (blocks) *blocks = c->sur_blocks;
+    if (fallbacks) *fallbacks = c->sur_fallbacks;
+    if (checks) *checks = c->sur_checks;
+    if (last_check_eps) *last_check_eps = c->sur_last_err;
     return WIG2_OK;
 }
 

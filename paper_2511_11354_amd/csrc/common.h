@@ -96,6 +96,37 @@ template <typename T>
 hipError_t launch_theta_panel(const ThetaArgs& a, const T* x, const T* y, T* out, int form,
                               double tau, hipStream_t st);
 
+// Learned pair-increment surrogate (surrogate.hip): per-point MLP with
+// kSurR anti-diagonal neighbours on each side, kSurH hidden units per layer.
+constexpr int kSurR = 8, kSurH = 16;
+constexpr int kSurD = 2 * kSurR + 1 + 3;
+constexpr int kSurP = kSurH * kSurD + kSurH + kSurH * kSurH + kSurH + kSurH + 1;
+struct SurScales {
+    float in_scale;       // multiplies f_t in the features
+    float out_scale;      // Delta = out_scale * y
+    float inv_out_scale;
+    float u_feat;         // pair-strength feature of the context
+};
+// One minibatch over samples idx = ((k0 + k) mod npts * mul + off) mod npts,
+// k < count (gcd(mul, npts) = 1 makes it a permutation).  Writes per
+// workgroup: the loss sum to lpart and, when train, the gradient sums to
+// partial[nwg][kSurP].
+template <typename T>
+hipError_t launch_sur_batch(const T* ft, const T* delta, int nx, int nk, long npts, long k0, long count,
+                            long mul, long off, const SurScales& sc, const float* params, float* partial,
+                            float* lpart, bool train, hipStream_t st);
+// Reduce the partials (times gscale) and take one Adam step; with grad_out
+// only write the reduced gradient there.
+hipError_t launch_sur_adam(float* params, float* mom, float* var, unsigned short* pbf, const float* partial,
+                           int nwg, float gscale, float lr, int step, float* grad_out, hipStream_t st);
+// f += out_scale * NN(ft) with the BF16 weights.
+template <typename T>
+hipError_t launch_sur_apply(const T* ft, T* f, int nx, int nk, const SurScales& sc, const unsigned short* pbf,
+                            hipStream_t st);
+// d = a - b (d may be NULL); part[2 w] = max|a - b|, part[2 w + 1] = max|b| per workgroup.
+template <typename T>
+hipError_t launch_diff_max(const T* a, const T* b, T* d, long n, float* part, int nwg, hipStream_t st);
+
 // Per-plane moments: s0 = sum w w f, skin = sum w w f (p1^2+p2^2)/2m,
 // s2 = sum w w f^2 (each [nx*nx]); rows[pl][n1] = sum_n2 w f (optional).
 template <typename T>

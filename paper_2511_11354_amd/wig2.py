@@ -41,6 +41,14 @@ class Obs(ctypes.Structure):
                 ("entropy_vn", ctypes.c_double), ("fallbacks", ctypes.c_int32)]
 
 
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("radius", ctypes.c_int32), ("hidden", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+SUR_PARAMS = 625  # W1[16][20], b1[16], W2[16][16], b2[16], w3[16], b3
+
 PROF_NAMES = ("advect_x1", "advect_x2", "theta_stage1", "theta_stage2", "meanfield")
 
 FN1 = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_double, ctypes.c_void_p)
@@ -80,6 +88,21 @@ SIGNATURES = {
                         ctypes.c_int),
     "wig2_batch_destroy": ([_vp], None),
     "wig2_batch_last_error": ([_vp], ctypes.c_char_p),
+    "wig2_surrogate_create": ([ctypes.POINTER(TrainCfg), ctypes.POINTER(_vp)], ctypes.c_int),
+    "wig2_surrogate_destroy": ([_vp], None),
+    "wig2_surrogate_last_error": ([_vp], ctypes.c_char_p),
+    "wig2_surrogate_collect": ([_vp, _vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "wig2_surrogate_stats": ([_vp, _dp, _dp, ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "wig2_surrogate_get_params": ([_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+                                  ctypes.c_int),
+    "wig2_surrogate_set_params": ([_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+                                  ctypes.c_int),
+    "wig2_surrogate_grad": ([_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_float), _dp], ctypes.c_int),
+    "wig2_surrogate_attach": ([_vp, _vp, ctypes.c_double, ctypes.c_int32], ctypes.c_int),
+    "wig2_surrogate_detach": ([_vp], ctypes.c_int),
+    "wig2_surrogate_report": ([_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(ctypes.c_int64), _dp], ctypes.c_int),
     "wig2_destroy": ([_vp], None),
     "wig2_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "wig2_last_error": ([_vp], ctypes.c_char_p),
@@ -236,6 +259,25 @@ class Solver:
             self._check(r, "wig2_theta_path")
         return {1: "general", 2: "stream", 3: "panel"}[r]
 
+    def attach_surrogate(self, model, drift_tol=1e-6, exact_check_every=8):
+        """Advance whole blocks with the learned pair increment (exact
+        fallback when mass or energy drift by more than drift_tol)."""
+        self._sur = model
+        self._check(self._L.wig2_surrogate_attach(self._h, model._h, float(drift_tol),
+                                                  int(exact_check_every)), "wig2_surrogate_attach")
+
+    def detach_surrogate(self):
+        self._check(self._L.wig2_surrogate_detach(self._h), "wig2_surrogate_detach")
+        self._sur = None
+
+    def surrogate_report(self):
+        b, f, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        e = ctypes.c_double()
+        self._check(self._L.wig2_surrogate_report(self._h, ctypes.byref(b), ctypes.byref(f),
+                                                  ctypes.byref(c), ctypes.byref(e)),
+                    "wig2_surrogate_report")
+        return {"blocks": b.value, "fallbacks": f.value, "checks": c.value, "last_check_eps": e.value}
+
     def band(self):
         b = self._L.wig2_band(self._h)
         if b < 0:
@@ -334,3 +376,69 @@ class Batch:
         cls = (16, 32, 48, 64, 96, 128)
         return {"points": tp.value, "theta_grid": dict(zip(cls, list(tg))),
                 "advect_grid": dict(zip(cls, list(ag))), "planes_per_group": dict(zip(cls, list(pp)))}
+
+
+class Surrogate:
+    """Learned pair-increment model (wig2_surrogate_*): create, collect /
+    train on a Solver's exact trajectory, attach to a Solver."""
+
+    def __init__(self, *, block=8, epochs=2, batch=65536, lr=3e-3, seed=0):
+        self._L = lib()
+        self.cfg = TrainCfg(8, 16, block, epochs, batch, lr, seed)
+        h = ctypes.c_void_p()
+        rc = self._L.wig2_surrogate_create(ctypes.byref(self.cfg), ctypes.byref(h))
+        if rc != OK:
+            raise Wig2Error(rc, f"wig2_surrogate_create: {self._L.wig2_strerror(rc).decode()}")
+        self._h = h
+
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = self._L.wig2_surrogate_last_error(self._h).decode() or self._L.wig2_strerror(rc).decode()
+            raise Wig2Error(rc, f"{what}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.wig2_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def collect(self, solver, blocks=1, train=True):
+        self._check(self._L.wig2_surrogate_collect(self._h, solver._h, int(blocks), int(train)),
+                    "wig2_surrogate_collect")
+
+    def stats(self):
+        tl, el = ctypes.c_double(), ctypes.c_double()
+        up, sm = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._L.wig2_surrogate_stats(self._h, ctypes.byref(tl), ctypes.byref(el),
+                                                 ctypes.byref(up), ctypes.byref(sm)), "wig2_surrogate_stats")
+        return {"train_loss": tl.value, "eval_loss": el.value, "updates": up.value, "samples": sm.value}
+
+    def get_params(self):
+        p = np.zeros(SUR_PARAMS, dtype=np.float32)
+        sc = np.zeros(3, dtype=np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._check(self._L.wig2_surrogate_get_params(self._h, p.ctypes.data_as(fp), sc.ctypes.data_as(fp)),
+                    "wig2_surrogate_get_params")
+        return p, sc
+
+    def set_params(self, params=None, scales=None):
+        fp = ctypes.POINTER(ctypes.c_float)
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        sc = None if scales is None else np.ascontiguousarray(scales, dtype=np.float32)
+        self._check(self._L.wig2_surrogate_set_params(self._h, None if p is None else p.ctypes.data_as(fp),
+                                                      None if sc is None else sc.ctypes.data_as(fp)),
+                    "wig2_surrogate_set_params")
+
+    def grad(self, solver, ft_dev, delta_dev):
+        """Gradient of the mean squared error over all points (device fields)."""
+        g = np.zeros(SUR_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(self._L.wig2_surrogate_grad(self._h, solver._h, _dev(ft_dev), _dev(delta_dev),
+                                                g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                ctypes.byref(loss)), "wig2_surrogate_grad")
+        return g, loss.value
