@@ -106,6 +106,76 @@ def cpu_baseline(w, f0, budget_s=20.0):
             "s_per_step_extrapolated": t_step}
 
 
+def bench_surrogate(a):
+    """Learned pair-increment surrogate at the periodic 128^4 shape (FP32):
+    train on blocks of ensemble instances (seeds 1000+), then advance the
+    same number of blocks from the mixture state (seed 0) exactly and with
+    the surrogate attached (drift tolerance 1e-6, exact check every 8
+    blocks); report both rates, the fallbacks and the final eps_inf of the
+    surrogate run against the exact one."""
+    import numpy as np
+    import torch
+
+    from paper_2511_11354_amd import inputs as I
+    from paper_2511_11354_amd import wig2
+
+    prec = a.precision or "fp32"
+    B = 8
+    model = wig2.Surrogate(block=B, epochs=2, batch=65536, lr=3e-3, seed=0)
+    t0 = time.perf_counter()
+    ens = I.ensemble()
+    train_ids = [i for i, w in enumerate(ens) if w.nx >= 48 and w.nk >= 48][:3]
+    for i in train_ids:
+        w = ens[i]
+        s = wig2.Solver(w.nx, w.nk, dt=w.dt, precision=prec)
+        s.set_potentials(w.vext, w.v12)
+        x, p, _ = s.nodes()
+        s.set_state(I.mixture(x, p, seed=w.extra["seed"], period=20.0))
+        model.collect(s, blocks=2, train=True)
+        s.close()
+    t_train = time.perf_counter() - t0
+    st = model.stats()
+
+    w = I.large_periodic(u=1.0)
+    runs = {}
+    nblocks = max(1, a.steps // B)
+    f0 = None
+    for mode in ("exact", "surrogate"):
+        s = wig2.Solver(w.nx, w.nk, dt=w.dt, precision=prec)
+        s.set_potentials(w.vext, w.v12)
+        if f0 is None:
+            x, p, _ = s.nodes()
+            f0 = I.mixture(x, p, seed=0, period=20.0)
+        s.set_state(f0)
+        s.step(B)  # warm-up block (exact)
+        if mode == "surrogate":
+            s.attach_surrogate(model, drift_tol=1e-6, exact_check_every=8)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.step(nblocks * B)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        runs[mode] = {"solver": s, "seconds": dt, "value": w.points * nblocks * B / dt}
+    fe, fs = runs["exact"]["solver"].get_state(), runs["surrogate"]["solver"].get_state()
+    eps = float(np.abs(fs - fe).max() / np.abs(fe).max())
+    rep = runs["surrogate"]["solver"].surrogate_report()
+    out = {
+        "metric": METRIC, "value": runs["surrogate"]["value"], "unit": "point-updates/s", "n_gpus": 1,
+        "steps": nblocks * B, "warmup": B, "ms_per_step": runs["surrogate"]["seconds"] / (nblocks * B) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec],
+        "data": "synthetic",
+        "config": {"workload": w.name + "-surrogate", "nx": w.nx, "nk": w.nk, "points": w.points,
+                   "dt": w.dt, "block": B, "drift_tol": 1e-6, "exact_check_every": 8,
+                   "train_instances": [ens[i].name for i in train_ids], "seed": 0},
+        "exact": {"value": runs["exact"]["value"],
+                  "ms_per_step": runs["exact"]["seconds"] / (nblocks * B) * 1e3},
+        "speedup_vs_exact": runs["exact"]["seconds"] / runs["surrogate"]["seconds"],
+        "surrogate": dict(rep, eps_inf_vs_exact=eps, train_seconds=t_train, **st),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def bench_ensemble(a):
     """64 uneven periodic instances (seeds 1000..1063): one batched step of
     the whole ensemble per 'step', FP32, against a loop over 64 single
@@ -193,9 +263,11 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x2"],
                     help="default: fp64 for the single-grid workloads, fp32 for the ensemble")
     ap.add_argument("--scheme", default="strang", choices=["strang", "lawson"])
-    ap.add_argument("--workload", default="large", choices=["large", "tiny", "ensemble", "box"],
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "tiny", "ensemble", "box", "surrogate"],
                     help="large: periodic 128^4 (default); tiny: periodic 32^4; ensemble: 64 "
-                         "uneven periodic instances; box: 129^2 x 256^2 SEM box")
+                         "uneven periodic instances; box: 129^2 x 256^2 SEM box; surrogate: "
+                         "128^4 FP32 with the learned pair increment")
     ap.add_argument("--potential", default="harmonic", choices=["harmonic", "double_well"],
                     help="V_ext of the box workload")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "profiles", "tune_cache.json"),
@@ -219,6 +291,8 @@ def main():
     if a.workload == "ensemble":
         a.precision = a.precision or "fp32"
         return bench_ensemble(a)
+    if a.workload == "surrogate":
+        return bench_surrogate(a)
     box = a.workload == "box"
     a.precision = a.precision or ("fp32" if box else "fp64")
     if box:
