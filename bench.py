@@ -48,6 +48,8 @@ def kernel_model(name, npts, elem, nk, band, precision, dense=False):
         return 2 * elem * npts, fl          # read f, write Theta f
     if name == "theta_stage2":
         return 3 * elem * npts, fl + 4 * npts  # read the two states, write the Heun result
+    if name == "theta_heun":
+        return 2 * elem * npts, 2 * fl + 6 * npts  # both Heun stages: read f, write f+
     return elem * npts, 4.0 * npts
 
 

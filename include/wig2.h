@@ -162,7 +162,8 @@ enum {
     WIG2_PROF_THETA_STAGE1 = 2, /* general: Theta[f];  stream: f + tau Theta[f]   */
     WIG2_PROF_THETA_STAGE2 = 3, /* second Heun stage (both kernels)               */
     WIG2_PROF_MEANFIELD = 4,    /* density moments + mean-field symbols     */
-    WIG2_PROF_N = 5
+    WIG2_PROF_THETA_HEUN = 5,   /* stream, Strang: both Heun stages in one pass */
+    WIG2_PROF_N = 6
 };
 int wig2_profile(wig2_ctx* ctx, int32_t enable);
 int wig2_profile_read(wig2_ctx* ctx, double* ms, int64_t* counts, int32_t reset);
@@ -180,7 +181,9 @@ int wig2_band(const wig2_ctx* ctx);
  * torus, FP64 or FP32, nk in {32, 48, 64, 96, 128} and a single-body band of
  * at most 4 modes (e.g. V_ext = V0 cos(2 pi x / L)).  Its Heun step is
  * g = f + dt Theta f, f' = (f + g)/2 + (dt/2) Theta g, equal to the general
- * kernels' f + (dt/2)(Theta f + Theta g) up to rounding.
+ * kernels' f + (dt/2)(Theta f + Theta g) up to rounding; with the Strang
+ * scheme both Heun stages run in one pass per plane (f read and f' written
+ * once; the plane stays in LDS between the two applications of Theta).
  * WIG2_THETA_AUTO (default): the streaming kernel whenever it applies.
  * wig2_set_theta_path returns WIG2_ENOTSUP for STREAM when the current
  * potentials rule it out (the choice then stays unchanged); with AUTO or

@@ -61,17 +61,13 @@ __device__ inline LineMap line_map(long line, int nx, int nk, int dim)
 // Handles displacements |c| <= 1 cell (taps d in [-2, 2]).
 // ---------------------------------------------------------------------------
 template <typename T, int NX, bool PER>
-__device__ __forceinline__ void advect_line_reg(const T* __restrict__ in, T* __restrict__ out,
-                                                int nk, int dim, long line, double cpp,
-                                                const double* __restrict__ pn,
-                                                const double* __restrict__ thomas)
+__device__ __forceinline__ void advect_line_core(const T* __restrict__ in, long ib, long is,
+                                                 T* __restrict__ out, long ob, long os, double c,
+                                                 const double* __restrict__ thomas)
 {
-    const LineMap lm = line_map(line, NX, nk, dim);
-    const double c = cpp * pn[lm.nv];  // displacement in cells
-
     T v[NX];
 #pragma unroll
-    for (int i = 0; i < NX; ++i) v[i] = in[lm.base + (long)i * lm.stride];
+    for (int i = 0; i < NX; ++i) v[i] = in[ib + (long)i * is];
 
     T em1 = T(0), eN = T(0);  // box: eta_{-1}, eta_{NX}
     T scale;
@@ -151,8 +147,52 @@ __device__ __forceinline__ void advect_line_reg(const T* __restrict__ in, T* __r
             const double u = (double)i - c;
             if (u < 0.0 || u > (double)(NX - 1)) acc = T(0);
         }
-        out[lm.base + (long)i * lm.stride] = acc;
+        out[ob + (long)i * os] = acc;
     }
+}
+
+template <typename T, int NX, bool PER>
+__device__ __forceinline__ void advect_line_reg(const T* __restrict__ in, T* __restrict__ out,
+                                                int nk, int dim, long line, double cpp,
+                                                const double* __restrict__ pn,
+                                                const double* __restrict__ thomas)
+{
+    const LineMap lm = line_map(line, NX, nk, dim);
+    advect_line_core<T, NX, PER>(in, lm.base, lm.stride, out, lm.base, lm.stride, cpp * pn[lm.nv],
+                                 thomas);
+}
+
+// One sweep over the lines of a slab of momentum rows n1 in [n1_0, n1_0 + ch)
+// (all other x, all n2).  Arrays are viewed as [nx][nx][nr][nk] holding the
+// rows n1 - off: the full state has nr = nk, off = 0; a slab buffer has
+// nr = ch, off = n1_0.  Pairing an x1 sweep of a slab (state -> slab buffer)
+// with the x2 sweep of the same slab (slab buffer -> state) keeps the
+// intermediate small enough to stay in the last-level cache.
+template <typename T, int NX>
+__global__ __launch_bounds__(64) void k_advect_slab(const T* __restrict__ in, T* __restrict__ out,
+                                                    int nk, int dim, int n1_0, int ch, int in_nr,
+                                                    int in_off, int out_nr, int out_off, double cpp,
+                                                    const double* __restrict__ pn)
+{
+    const long line = (long)blockIdx.x * 64 + threadIdx.x;
+    const long per = (long)ch * nk;
+    if (line >= (long)NX * per) return;
+    const int o = (int)(line / per);
+    const int rem = (int)(line % per);
+    const int n1 = n1_0 + rem / nk, n2 = rem % nk;
+    long ib, is, ob, os;
+    if (dim == 1) {  // along i1 at fixed i2 = o
+        ib = ((long)o * in_nr + n1 - in_off) * nk + n2;
+        is = (long)NX * in_nr * nk;
+        ob = ((long)o * out_nr + n1 - out_off) * nk + n2;
+        os = (long)NX * out_nr * nk;
+    } else {  // along i2 at fixed i1 = o
+        ib = ((long)o * NX * in_nr + n1 - in_off) * nk + n2;
+        is = (long)in_nr * nk;
+        ob = ((long)o * NX * out_nr + n1 - out_off) * nk + n2;
+        os = (long)out_nr * nk;
+    }
+    advect_line_core<T, NX, true>(in, ib, is, out, ob, os, cpp * pn[dim == 1 ? n1 : n2], nullptr);
 }
 
 template <typename T, int NX, bool PER>
@@ -371,6 +411,40 @@ hipError_t launch_advect(const T* in, T* out, T* work, int nx, int nk, int dim, 
                            nk, dim, nl, cpp, p_dev, thomas_dev);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_advect_pair_slabs(T* f, T* slab, int nx, int nk, int ch, double cpp, const double* p_dev,
+                                   hipStream_t st)
+{
+    if (ch <= 0 || nk % ch) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)(((long)nx * ch * nk + 63) / 64);
+    for (int n1_0 = 0; n1_0 < nk; n1_0 += ch) {
+#define WIG2_SLAB(N)                                                                                    \
+    case N:                                                                                             \
+        hipLaunchKernelGGL((k_advect_slab<T, N>), dim3(nb), dim3(64), 0, st, f, slab, nk, 1, n1_0, ch, nk, \
+                           0, ch, n1_0, cpp, p_dev);                                                    \
+        hipLaunchKernelGGL((k_advect_slab<T, N>), dim3(nb), dim3(64), 0, st, slab, f, nk, 2, n1_0, ch, ch, \
+                           n1_0, nk, 0, cpp, p_dev);                                                    \
+        break;
+        switch (nx) {
+            WIG2_SLAB(16)
+            WIG2_SLAB(32)
+            WIG2_SLAB(48)
+            WIG2_SLAB(64)
+            WIG2_SLAB(96)
+            WIG2_SLAB(128)
+        default: return hipErrorInvalidValue;
+        }
+#undef WIG2_SLAB
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+template hipError_t launch_advect_pair_slabs<double>(double*, double*, int, int, int, double, const double*,
+                                                     hipStream_t);
+template hipError_t launch_advect_pair_slabs<float>(float*, float*, int, int, int, double, const double*,
+                                                    hipStream_t);
 
 template hipError_t launch_advect<double>(const double*, double*, double*, int, int, int, bool,
                                           double, double, const double*, const double*,

@@ -260,7 +260,8 @@ hipError_t step_once(wig2_ctx* c)
         return timed(c, WIG2_PROF_MEANFIELD, [&] { return update_meanfield<T>(c, a, b, tb); });
     };
     auto THS = [&](const T* x, const T* y, T* out, int form) {
-        return timed(c, form == 1 ? WIG2_PROF_THETA_STAGE1 : WIG2_PROF_THETA_STAGE2,
+        return timed(c, form == 3 ? WIG2_PROF_THETA_HEUN
+                                  : form == 1 ? WIG2_PROF_THETA_STAGE1 : WIG2_PROF_THETA_STAGE2,
                      [&] { return theta_form<T>(c, x, y, out, form, tau); });
     };
     if (use_forms(c)) {
@@ -271,8 +272,12 @@ hipError_t step_once(wig2_ctx* c)
             STEPCHK(ADV(1, 0.5 * tau, f, tmp));
             STEPCHK(ADV(2, 0.5 * tau, tmp, f));
             if (c->meanfield) STEPCHK(MF(f, nullptr, 0.0));
-            STEPCHK(THS(f, nullptr, k1, 1));
-            STEPCHK(THS(k1, f, f, 2));
+            if (use_stream(c)) {
+                STEPCHK(THS(f, nullptr, f, 3));
+            } else {
+                STEPCHK(THS(f, nullptr, k1, 1));
+                STEPCHK(THS(k1, f, f, 2));
+            }
             STEPCHK(ADV(1, 0.5 * tau, f, tmp));
             STEPCHK(ADV(2, 0.5 * tau, tmp, f));
         } else {

@@ -55,6 +55,14 @@ hipError_t launch_advect(const T* in, T* out, T* work, int nx, int nk, int dim, 
                          double cells_per_p, double max_cells, const double* p_dev,
                          const double* thomas_dev, hipStream_t st);
 
+// Both half-step sweeps (x1 then x2) of a torus state in place, slab by slab
+// of ch momentum rows n1: x1 sweep state -> slab buffer (nx*nx*ch*nk
+// elements), x2 sweep slab buffer -> state.  Register-resident nx only,
+// displacement <= 1 cell.
+template <typename T>
+hipError_t launch_advect_pair_slabs(T* f, T* slab, int nx, int nk, int ch, double cpp, const double* p_dev,
+                                   hipStream_t st);
+
 // Theta application on all nx*nx planes.
 //   mode 0: out = Theta[u]
 //   mode 1: out = u + tau/2 (v + Theta[u + tau v])   (out may equal u)
@@ -81,6 +89,7 @@ hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int 
 //   form 0: out = Theta[x]
 //   form 1: out = x + tau Theta[x]
 //   form 2: out = (y + x)/2 + (tau/2) Theta[x]
+//   form 3: out = x + (tau/2)(Theta[x] + Theta[x + tau Theta[x]])  (Heun)
 // out may alias x or y.
 bool theta_stream_ok(const ThetaArgs& a);
 template <typename T>

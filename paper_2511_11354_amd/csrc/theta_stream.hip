@@ -16,6 +16,10 @@
 //   form 0: out = Theta[x]
 //   form 1: out = x + tau Theta[x]
 //   form 2: out = (y + x)/2 + (tau/2) Theta[x]
+//   form 3: out = x + (tau/2)(Theta[x] + Theta[x + tau Theta[x]]), the whole
+//           Heun step with the plane kept in LDS between the two passes
+//           (Theta acts within each x-pair plane), so f is read and the
+//           result written once.
 // Heun's step f + (tau/2)(Theta f + Theta g), g = f + tau Theta f, is form 1
 // followed by form 2 with x = g, y = f, because (tau/2) Theta f = (g - f)/2.
 // out may alias x or y: plane p of x is read (into registers) one iteration
@@ -61,14 +65,14 @@ struct StreamLayout {
 
 // Waves per SIMD to budget registers for: FP32 planes of 128 fit twice in
 // LDS, so two 8-wave workgroups share a CU when a wave stays within 128 VGPRs.
-template <typename T, int NK>
+template <typename T, int NK, int FORM>
 constexpr int stream_waves_per_eu()
 {
-    return (sizeof(T) == 4 && NK == 128) ? 4 : 1;
+    return (sizeof(T) == 4 && NK == 128 && FORM != 3) ? 4 : 1;
 }
 
 template <typename T, int NK, bool TWO, int FORM>
-__global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK>())) void k_theta_stream(
+__global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>())) void k_theta_stream(
     const T* x, const T* y, T* out, int nx, long np, const double* __restrict__ sig1,
     const double* __restrict__ sig2, int band, const double* __restrict__ kap, double tau)
 {
@@ -103,9 +107,12 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK>())) void 
     if (pl >= np) return;  // whole workgroup leaves together
     const long stride = gridDim.x;
 
-    // registers of the plane to be written to LDS next
+    // registers of the plane to be written to LDS next.  Nothing consumes
+    // them before the next iteration, so the loads stay in flight across the
+    // matrix-core work (any arithmetic on a loaded value here would make the
+    // wave wait for every load issued before it).
     VT xr[NV];
-    T tkv = T(0);
+    double kraw = 0.0;  // kap[l][|d|] of the next plane, d = tid - NK
     auto fetch = [&](long p) {
         const VT* src = reinterpret_cast<const VT*>(x + p * (long)NK * NK);
 #pragma unroll
@@ -115,56 +122,36 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK>())) void 
                 const int i1 = (int)(p / nx), i2 = (int)(p % nx);
                 const int ell = (i1 - i2 + nx) % nx;
                 const int d = tid - NK, ad = d < 0 ? -d : d;
-                tkv = (ad > 0 && ad < NK) ? sgnval(d, T(kap[(long)ell * NK + ad])) : T(0);
+                kraw = kap[(long)ell * NK + min(max(ad, 1), NK - 1)];
             }
         }
     };
-    fetch(pl);
+    // The one-pass Heun form holds h = f + tau/2 Theta f in registers
+    // instead of the next plane: it loads each plane at the top of its
+    // iteration.
+    constexpr bool PREFETCH = FORM != 3;
+    if constexpr (PREFETCH) fetch(pl);
 
     for (; pl < np; pl += stride) {
+        if constexpr (!PREFETCH) fetch(pl);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int e = (tid + v * NT) * VN;
             *reinterpret_cast<VT*>(X + (e / NK) * LD + e % NK) = xr[v];
         }
         if constexpr (TWO) {
-            if (tid < 2 * NK) tk[tid] = tkv;
+            if (tid < 2 * NK) {
+                const int d = tid - NK, ad = d < 0 ? -d : d;
+                tk[tid] = (ad > 0 && ad < NK) ? sgnval(d, T(kraw)) : T(0);
+            }
         }
         __syncthreads();
-        if (pl + stride < np) fetch(pl + stride);
+        if constexpr (PREFETCH) {
+            if (pl + stride < np) fetch(pl + stride);
+        }
 
         const int i1 = (int)(pl / nx), i2 = (int)(pl % nx);
         const long pbase = pl * (long)NK * NK;
-
-        V sacc[NS];
-#pragma unroll
-        for (int j = 0; j < NS; ++j) sacc[j] = V{0, 0, 0, 0};
-        if constexpr (TWO) {
-            // Output tile (row block w, skewed tile j) covers s in
-            // [16(w+j), 16(w+j)+16); the 16 rows k of block KB hold non-zero
-            // H[k][s] = X[k][s - k] for that tile iff 0 <= w + j - KB <= NW.
-            // A = tk[r - k + NK] (r = 16w + li), B = X[k LD + s - k] (zero gaps
-            // outside the plane).
-            const T* pa = tk + 16 * w + li + NK - lk;
-            const T* pb = X + lk * (LD - 1) + 16 * w + li;
-#pragma unroll
-            for (int KB = 0; KB < NW; ++KB) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int kb = 4 * KB + i;
-                    const T a = pa[-4 * kb];
-#pragma unroll
-                    for (int j = 0; j < NS; ++j) {
-                        const int d = w + j - KB;
-                        if (d < 0 || d > NW) continue;  // wave-uniform
-                        sacc[j] = mma(a, pb[4 * kb * (LD - 1) + 16 * j], sacc[j]);
-                    }
-                }
-                // keep the scheduler from hoisting every operand read of
-                // the unrolled loop (register pressure)
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
 
         // Lane-owned points: accumulator element (j, q) is the point
         // n1 = 16w + acc_row(lk, q), n2 = 16(w + j) + li - n1 when 0 <= n2 < NK.
@@ -185,25 +172,100 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK>())) void 
         auto row = [&](int q) { return 16 * w + acc_row<T>(el >> 4, q); };
         auto lds_at = [&](int j, int q) { return X + row(q) * LD + col(j, q); };
 
-        // single-body differences (modes 1..band of x_i1 along n1, of x_i2
-        // along n2), added onto the pair-term accumulators
-        for (int m = 1; m <= band; ++m) {
+        // acc = Theta of the plane held in X, at the lane-owned points
+        auto theta_pass = [&](V (&acc)[NS]) {
+#pragma unroll
+            for (int j = 0; j < NS; ++j) acc[j] = V{0, 0, 0, 0};
+            if constexpr (TWO) {
+                // Output tile (row block w, skewed tile j) covers s in
+                // [16(w+j), 16(w+j)+16); the 16 rows k of block KB hold non-zero
+                // H[k][s] = X[k][s - k] for that tile iff 0 <= w + j - KB <= NW.
+                // A = tk[r - k + NK] (r = 16w + li), B = X[k LD + s - k] (zero gaps
+                // outside the plane).
+                const T* pa = tk + 16 * w + li + NK - lk;
+                const T* pb = X + lk * (LD - 1) + 16 * w + li;
+#pragma unroll
+                for (int KB = 0; KB < NW; ++KB) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int kb = 4 * KB + i;
+                        const T a = pa[-4 * kb];
+#pragma unroll
+                        for (int j = 0; j < NS; ++j) {
+                            const int d = w + j - KB;
+                            if (d < 0 || d > NW) continue;  // wave-uniform
+                            acc[j] = mma(a, pb[4 * kb * (LD - 1) + 16 * j], acc[j]);
+                        }
+                        // the one-pass Heun form also holds h: fewer reads in flight
+                        if constexpr (FORM == 3) __builtin_amdgcn_sched_barrier(0);
+                    }
+                    // keep the scheduler from hoisting every operand read of
+                    // the unrolled loop (register pressure)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            // single-body differences (modes 1..band of x_i1 along n1, of x_i2
+            // along n2), added onto the pair-term accumulators
+            for (int m = 1; m <= band; ++m) {
+                el = opaque_lane();
+                const T s1 = T(sig1[(long)i1 * NK + m]);
+                const T s2 = T(sig2[(long)i2 * NK + m]);
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const T* xp = lds_at(j, q);
+                        acc[j][q] += s1 * (xp[-m * LD] - xp[m * LD]) + s2 * (xp[-m] - xp[m]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        };
+
+        V sacc[NS];
+        theta_pass(sacc);
+
+        if constexpr (FORM == 3) {
+            // Whole Heun step in one pass over the plane: h = f + tau/2 Theta f
+            // stays in registers, g = f + tau Theta f replaces f in LDS, and
+            // the second pass gives f' = h + tau/2 Theta g.
+            V hv[NS];
             el = opaque_lane();
-            const T s1 = T(sig1[(long)i1 * NK + m]);
-            const T s2 = T(sig2[(long)i2 * NK + m]);
+#pragma unroll
+            for (int j = 0; j < NS; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const T fx = *lds_at(j, q);
+                    hv[j][q] = fx + T(0.5 * tau) * sacc[j][q];
+                    sacc[j][q] = fx + T(tau) * sacc[j][q];
+                }
+            __syncthreads();  // every wave is done reading f
+            el = opaque_lane();
+#pragma unroll
+            for (int j = 0; j < NS; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int n2 = col(j, q);
+                    if (n2 >= 0 && n2 < NK) *lds_at(j, q) = sacc[j][q];
+                }
+            __syncthreads();
+            theta_pass(sacc);
+            el = opaque_lane();
 #pragma unroll
             for (int j = 0; j < NS; ++j) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const T* xp = lds_at(j, q);
-                    sacc[j][q] += s1 * (xp[-m * LD] - xp[m * LD]) + s2 * (xp[-m] - xp[m]);
+                    const int n1 = row(q), n2 = col(j, q);
+                    if (n2 >= 0 && n2 < NK) out[pbase + (long)n1 * NK + n2] = hv[j][q] + T(0.5 * tau) * sacc[j][q];
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
+            __syncthreads();  // LDS plane is rewritten next iteration
+            continue;
         }
 
         // epilogue and store; y (form 2) is fetched one group of tiles ahead
-        constexpr int YG = sizeof(T) == 4 ? 1 : 2;
+        constexpr int YG = 1;
         constexpr int NG = (NS + YG - 1) / YG;
         T yv[2][YG][4];
         auto fetch_y = [&](int g, T (&dst)[YG][4]) {
@@ -278,6 +340,7 @@ hipError_t go_stream_form(const ThetaArgs& a, const T* x, const T* y, T* out, in
     case 0: return go_stream<T, NK, TWO, 0>(a, x, y, out, tau, st);
     case 1: return go_stream<T, NK, TWO, 1>(a, x, y, out, tau, st);
     case 2: return go_stream<T, NK, TWO, 2>(a, x, y, out, tau, st);
+    case 3: return go_stream<T, NK, TWO, 3>(a, x, y, out, tau, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -42,7 +42,7 @@ def kernel_class(name: str):
     m = re.match(r"k_theta_stream<(\w+), (\d+), (\w+), (\d)>", n)
     if m:
         form = int(m.group(4))
-        cls = {0: "theta_apply", 1: "theta_stage1", 2: "theta_stage2"}[form]
+        cls = {0: "theta_apply", 1: "theta_stage1", 2: "theta_stage2", 3: "theta_heun"}[form]
         return cls, os.path.join(CSRC, "theta_stream.hip")
     m = re.match(r"k_theta<(\w+), (\d+), (\w+), (\w+), (\d)>", n)
     if m:

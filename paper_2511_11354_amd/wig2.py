@@ -49,7 +49,7 @@ class TrainCfg(ctypes.Structure):
 
 SUR_PARAMS = 625  # W1[16][20], b1[16], W2[16][16], b2[16], w3[16], b3
 
-PROF_NAMES = ("advect_x1", "advect_x2", "theta_stage1", "theta_stage2", "meanfield")
+PROF_NAMES = ("advect_x1", "advect_x2", "theta_stage1", "theta_stage2", "meanfield", "theta_heun")
 
 FN1 = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_double, ctypes.c_void_p)
 _dp = ctypes.POINTER(ctypes.c_double)
