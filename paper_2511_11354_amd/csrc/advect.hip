@@ -162,39 +162,6 @@ __device__ __forceinline__ void advect_line_reg(const T* __restrict__ in, T* __r
                                  thomas);
 }
 
-// One sweep over the lines of a slab of momentum rows n1 in [n1_0, n1_0 + ch)
-// (all other x, all n2).  Arrays are viewed as [nx][nx][nr][nk] holding the
-// rows n1 - off: the full state has nr = nk, off = 0; a slab buffer has
-// nr = ch, off = n1_0.  Pairing an x1 sweep of a slab (state -> slab buffer)
-// with the x2 sweep of the same slab (slab buffer -> state) keeps the
-// intermediate small enough to stay in the last-level cache.
-template <typename T, int NX>
-__global__ __launch_bounds__(64) void k_advect_slab(const T* __restrict__ in, T* __restrict__ out,
-                                                    int nk, int dim, int n1_0, int ch, int in_nr,
-                                                    int in_off, int out_nr, int out_off, double cpp,
-                                                    const double* __restrict__ pn)
-{
-    const long line = (long)blockIdx.x * 64 + threadIdx.x;
-    const long per = (long)ch * nk;
-    if (line >= (long)NX * per) return;
-    const int o = (int)(line / per);
-    const int rem = (int)(line % per);
-    const int n1 = n1_0 + rem / nk, n2 = rem % nk;
-    long ib, is, ob, os;
-    if (dim == 1) {  // along i1 at fixed i2 = o
-        ib = ((long)o * in_nr + n1 - in_off) * nk + n2;
-        is = (long)NX * in_nr * nk;
-        ob = ((long)o * out_nr + n1 - out_off) * nk + n2;
-        os = (long)NX * out_nr * nk;
-    } else {  // along i2 at fixed i1 = o
-        ib = ((long)o * NX * in_nr + n1 - in_off) * nk + n2;
-        is = (long)in_nr * nk;
-        ob = ((long)o * NX * out_nr + n1 - out_off) * nk + n2;
-        os = (long)out_nr * nk;
-    }
-    advect_line_core<T, NX, true>(in, ib, is, out, ob, os, cpp * pn[dim == 1 ? n1 : n2], nullptr);
-}
-
 template <typename T, int NX, bool PER>
 __global__ __launch_bounds__(64) void k_advect_reg(const T* __restrict__ in, T* __restrict__ out,
                                                    int nk, int dim, long nlines, double cpp,
@@ -411,40 +378,6 @@ hipError_t launch_advect(const T* in, T* out, T* work, int nx, int nk, int dim, 
                            nk, dim, nl, cpp, p_dev, thomas_dev);
     return hipGetLastError();
 }
-
-template <typename T>
-hipError_t launch_advect_pair_slabs(T* f, T* slab, int nx, int nk, int ch, double cpp, const double* p_dev,
-                                   hipStream_t st)
-{
-    if (ch <= 0 || nk % ch) return hipErrorInvalidValue;
-    const unsigned nb = (unsigned)(((long)nx * ch * nk + 63) / 64);
-    for (int n1_0 = 0; n1_0 < nk; n1_0 += ch) {
-#define WIG2_SLAB(N)                                                                                    \
-    case N:                                                                                             \
-        hipLaunchKernelGGL((k_advect_slab<T, N>), dim3(nb), dim3(64), 0, st, f, slab, nk, 1, n1_0, ch, nk, \
-                           0, ch, n1_0, cpp, p_dev);                                                    \
-        hipLaunchKernelGGL((k_advect_slab<T, N>), dim3(nb), dim3(64), 0, st, slab, f, nk, 2, n1_0, ch, ch, \
-                           n1_0, nk, 0, cpp, p_dev);                                                    \
-        break;
-        switch (nx) {
-            WIG2_SLAB(16)
-            WIG2_SLAB(32)
-            WIG2_SLAB(48)
-            WIG2_SLAB(64)
-            WIG2_SLAB(96)
-            WIG2_SLAB(128)
-        default: return hipErrorInvalidValue;
-        }
-#undef WIG2_SLAB
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-template hipError_t launch_advect_pair_slabs<double>(double*, double*, int, int, int, double, const double*,
-                                                     hipStream_t);
-template hipError_t launch_advect_pair_slabs<float>(float*, float*, int, int, int, double, const double*,
-                                                    hipStream_t);
 
 template hipError_t launch_advect<double>(const double*, double*, double*, int, int, int, bool,
                                           double, double, const double*, const double*,

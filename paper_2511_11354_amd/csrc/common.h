@@ -55,14 +55,6 @@ hipError_t launch_advect(const T* in, T* out, T* work, int nx, int nk, int dim, 
                          double cells_per_p, double max_cells, const double* p_dev,
                          const double* thomas_dev, hipStream_t st);
 
-// Both half-step sweeps (x1 then x2) of a torus state in place, slab by slab
-// of ch momentum rows n1: x1 sweep state -> slab buffer (nx*nx*ch*nk
-// elements), x2 sweep slab buffer -> state.  Register-resident nx only,
-// displacement <= 1 cell.
-template <typename T>
-hipError_t launch_advect_pair_slabs(T* f, T* slab, int nx, int nk, int ch, double cpp, const double* p_dev,
-                                   hipStream_t st);
-
 // Theta application on all nx*nx planes.
 //   mode 0: out = Theta[u]
 //   mode 1: out = u + tau/2 (v + Theta[u + tau v])   (out may equal u)
