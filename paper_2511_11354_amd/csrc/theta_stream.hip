@@ -58,6 +58,7 @@ template <typename T, int NK>
 struct StreamLayout {
     static constexpr int PADR = kStreamBand;
     static constexpr int LD = NK + kPadCols;
+    static constexpr int PADC = LD - NK;
     static constexpr int X_ELEMS = (NK + 2 * PADR) * LD;
     static constexpr int TAB = 2 * NK;
     static constexpr size_t bytes = sizeof(T) * (size_t)(X_ELEMS + TAB);
@@ -65,14 +66,17 @@ struct StreamLayout {
 
 // Waves per SIMD to budget registers for: FP32 planes of 128 fit twice in
 // LDS, so two 8-wave workgroups share a CU when a wave stays within 128 VGPRs.
-template <typename T, int NK, int FORM>
+template <typename T, int NK, int FORM, int WS>
 constexpr int stream_waves_per_eu()
 {
-    return (sizeof(T) == 4 && NK == 128 && FORM != 3) ? 4 : 1;
+    return (sizeof(T) == 4 && NK == 128 && FORM != 3 && WS == 1) ? 4 : 1;
 }
 
-template <typename T, int NK, bool TWO, int FORM>
-__global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>())) void k_theta_stream(
+// WS waves share each 16-row block (WS = 2: 2 NK/16 waves per workgroup, each
+// with about half of the block's skewed tiles), trading registers per wave
+// for more waves to hide LDS and issue latency behind the matrix cores.
+template <typename T, int NK, bool TWO, int FORM, int WS>
+__global__ __launch_bounds__(NK / 16 * 64 * WS, (stream_waves_per_eu<T, NK, FORM, WS>())) void k_theta_stream(
     const T* x, const T* y, T* out, int nx, long np, const double* __restrict__ sig1,
     const double* __restrict__ sig2, int band, const double* __restrict__ kap, double tau)
 {
@@ -80,8 +84,9 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
     typedef typename Vec16<T>::V VT;
     typedef StreamLayout<T, NK> L;
     constexpr int NW = NK / 16;
-    constexpr int NT = NW * 64;
-    constexpr int NS = NW + 1;
+    constexpr int NT = NW * 64 * WS;
+    constexpr int NS = NW + 1;                // skewed tiles per row block
+    constexpr int NSH = (NS + WS - 1) / WS;   // of which one wave holds
     constexpr int LD = L::LD;
     constexpr int VN = Vec16<T>::N;
     constexpr int NV = NK * NK / (NT * VN);  // 16-byte loads per thread per plane
@@ -93,7 +98,10 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
     T* tk = Xbase + L::X_ELEMS;   // tk[d + NK] = sgn(d) kap[|d|]
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (scalar)
+    const int w = wv % NW;              // row block
+    const int J0 = (wv / NW) * NSH;     // first skewed tile of this wave
     const int li = lane & 15, lk = lane >> 4;
 
     // zero gaps once; plane writes never touch them
@@ -101,7 +109,7 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
         Xbase[e] = T(0);
         X[NK * LD + e] = T(0);
     }
-    for (int e = tid; e < NK * kPadCols; e += NT) X[(e / kPadCols) * LD + NK + e % kPadCols] = T(0);
+    for (int e = tid; e < NK * L::PADC; e += NT) X[(e / L::PADC) * LD + NK + e % L::PADC] = T(0);
 
     long pl = blockIdx.x;
     if (pl >= np) return;  // whole workgroup leaves together
@@ -153,8 +161,9 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
         const int i1 = (int)(pl / nx), i2 = (int)(pl % nx);
         const long pbase = pl * (long)NK * NK;
 
-        // Lane-owned points: accumulator element (j, q) is the point
-        // n1 = 16w + acc_row(lk, q), n2 = 16(w + j) + li - n1 when 0 <= n2 < NK.
+        // Lane-owned points: accumulator element (jj, q) is the point
+        // n1 = 16w + acc_row(lk, q), n2 = 16(w + j) + li - n1 of skewed tile
+        // j = J0 + jj, when j < NS and 0 <= n2 < NK.
         // Reads for points outside the plane hit the zero gaps (or clamp) and
         // their results are not stored.
         // Position arithmetic restarts from an opaque copy of the lane id in
@@ -166,16 +175,17 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
             return l;
         };
         int el = opaque_lane();
-        auto col = [&](int j, int q) {
-            return 16 * (w + j) + (el & 15) - (16 * w + acc_row<T>(el >> 4, q));
+        auto col = [&](int jj, int q) {
+            return 16 * (w + J0 + jj) + (el & 15) - (16 * w + acc_row<T>(el >> 4, q));
         };
+        auto tile_ok = [&](int jj) { return WS == 1 || J0 + jj < NS; };  // wave-uniform
         auto row = [&](int q) { return 16 * w + acc_row<T>(el >> 4, q); };
         auto lds_at = [&](int j, int q) { return X + row(q) * LD + col(j, q); };
 
         // acc = Theta of the plane held in X, at the lane-owned points
-        auto theta_pass = [&](V (&acc)[NS]) {
+        auto theta_pass = [&](V (&acc)[NSH]) {
 #pragma unroll
-            for (int j = 0; j < NS; ++j) acc[j] = V{0, 0, 0, 0};
+            for (int j = 0; j < NSH; ++j) acc[j] = V{0, 0, 0, 0};
             if constexpr (TWO) {
                 // Output tile (row block w, skewed tile j) covers s in
                 // [16(w+j), 16(w+j)+16); the 16 rows k of block KB hold non-zero
@@ -183,18 +193,25 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
                 // A = tk[r - k + NK] (r = 16w + li), B = X[k LD + s - k] (zero gaps
                 // outside the plane).
                 const T* pa = tk + 16 * w + li + NK - lk;
-                const T* pb = X + lk * (LD - 1) + 16 * w + li;
+                const T* pb = X + lk * (LD - 1) + 16 * (w + J0) + li;
 #pragma unroll
                 for (int KB = 0; KB < NW; ++KB) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int kb = 4 * KB + i;
                         const T a = pa[-4 * kb];
+                        // All operand reads are issued before the (scalar)
+                        // tile tests; reads of inactive tiles stay inside the
+                        // LDS allocation (columns -127 .. 255 of rows 0 .. NK-1)
+                        // and are not used.
+                        T bv[NSH];
 #pragma unroll
-                        for (int j = 0; j < NS; ++j) {
-                            const int d = w + j - KB;
-                            if (d < 0 || d > NW) continue;  // wave-uniform
-                            acc[j] = mma(a, pb[4 * kb * (LD - 1) + 16 * j], acc[j]);
+                        for (int j = 0; j < NSH; ++j) bv[j] = pb[4 * kb * (LD - 1) + 16 * j];
+#pragma unroll
+                        for (int j = 0; j < NSH; ++j) {
+                            const int d = w + J0 + j - KB;
+                            if (!tile_ok(j) || d < 0 || d > NW) continue;  // wave-uniform
+                            acc[j] = mma(a, bv[j], acc[j]);
                         }
                         // the one-pass Heun form also holds h: fewer reads in flight
                         if constexpr (FORM == 3) __builtin_amdgcn_sched_barrier(0);
@@ -211,7 +228,7 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
                 const T s1 = T(sig1[(long)i1 * NK + m]);
                 const T s2 = T(sig2[(long)i2 * NK + m]);
 #pragma unroll
-                for (int j = 0; j < NS; ++j) {
+                for (int j = 0; j < NSH; ++j) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const T* xp = lds_at(j, q);
@@ -222,17 +239,17 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
             }
         };
 
-        V sacc[NS];
+        V sacc[NSH];
         theta_pass(sacc);
 
         if constexpr (FORM == 3) {
             // Whole Heun step in one pass over the plane: h = f + tau/2 Theta f
             // stays in registers, g = f + tau Theta f replaces f in LDS, and
             // the second pass gives f' = h + tau/2 Theta g.
-            V hv[NS];
+            V hv[NSH];
             el = opaque_lane();
 #pragma unroll
-            for (int j = 0; j < NS; ++j)
+            for (int j = 0; j < NSH; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const T fx = *lds_at(j, q);
@@ -242,21 +259,22 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
             __syncthreads();  // every wave is done reading f
             el = opaque_lane();
 #pragma unroll
-            for (int j = 0; j < NS; ++j)
+            for (int j = 0; j < NSH; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int n2 = col(j, q);
-                    if (n2 >= 0 && n2 < NK) *lds_at(j, q) = sacc[j][q];
+                    if (tile_ok(j) && n2 >= 0 && n2 < NK) *lds_at(j, q) = sacc[j][q];
                 }
             __syncthreads();
             theta_pass(sacc);
             el = opaque_lane();
 #pragma unroll
-            for (int j = 0; j < NS; ++j) {
+            for (int j = 0; j < NSH; ++j) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int n1 = row(q), n2 = col(j, q);
-                    if (n2 >= 0 && n2 < NK) out[pbase + (long)n1 * NK + n2] = hv[j][q] + T(0.5 * tau) * sacc[j][q];
+                    if (tile_ok(j) && n2 >= 0 && n2 < NK)
+                        out[pbase + (long)n1 * NK + n2] = hv[j][q] + T(0.5 * tau) * sacc[j][q];
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -266,13 +284,13 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
 
         // epilogue and store; y (form 2) is fetched one group of tiles ahead
         constexpr int YG = 1;
-        constexpr int NG = (NS + YG - 1) / YG;
+        constexpr int NG = (NSH + YG - 1) / YG;
         T yv[2][YG][4];
         auto fetch_y = [&](int g, T (&dst)[YG][4]) {
 #pragma unroll
             for (int jj = 0; jj < YG; ++jj) {
                 const int j = g * YG + jj;
-                if (j >= NS) break;
+                if (j >= NSH) break;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int n1 = row(q);
@@ -291,7 +309,7 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
 #pragma unroll
             for (int jj = 0; jj < YG; ++jj) {
                 const int j = g * YG + jj;
-                if (j >= NS) break;
+                if (j >= NSH) break;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int n1 = row(q);
@@ -304,7 +322,7 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
                         o = *lds_at(j, q) + T(tau) * val;
                     else
                         o = T(0.5) * (yv[g & 1][jj][q] + *lds_at(j, q)) + T(0.5 * tau) * val;
-                    if (n2 >= 0 && n2 < NK) out[pbase + (long)n1 * NK + n2] = o;
+                    if (tile_ok(j) && n2 >= 0 && n2 < NK) out[pbase + (long)n1 * NK + n2] = o;
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -313,12 +331,20 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, FORM>()))
     }
 }
 
+// Waves per row block for each plane size and form.
+template <typename T, int NK, int FORM>
+constexpr int stream_ws()
+{
+    return 1;
+}
+
 template <typename T, int NK, bool TWO, int FORM>
 hipError_t go_stream(const ThetaArgs& a, const T* x, const T* y, T* out, double tau, hipStream_t st)
 {
-    auto kf = k_theta_stream<T, NK, TWO, FORM>;
+    constexpr int WS = stream_ws<T, NK, FORM>();
+    auto kf = k_theta_stream<T, NK, TWO, FORM, WS>;
     const size_t sm = StreamLayout<T, NK>::bytes;
-    const int nt = NK / 16 * 64;
+    const int nt = NK / 16 * 64 * WS;
     hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
     if (e != hipSuccess) return e;
     int dev = 0, ncu = 0, per = 0;
