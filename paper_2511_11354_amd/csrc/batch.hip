@@ -71,6 +71,7 @@ struct wig2_batch {
         int nx, nk;
         int th_begin, th_count, adv_begin, adv_count;
         int th_grid, adv_grid;
+        bool stream;  // Theta by the streaming one-pass Heun kernel
     };
     std::vector<Cls> cls;                         // size classes (nx, nk)
     std::map<std::pair<int, int>, std::pair<int, int>> grids;  // (nx,nk) -> (theta, sweep) grid
@@ -137,8 +138,13 @@ int build_items(wig2_batch* b)
     b->cls.clear();
     for (auto& kv : chains) {
         const int nx = kv.first.first, nk = kv.first.second;
-        const int P = std::max(1, std::min(b->planes[nk], batch_theta_max_planes(nk, b->elem)));
-        wig2_batch::Cls c{nx, nk, (int)thv.size(), 0, (int)av.size(), 0, 4 * b->ncu, 8 * b->ncu};
+        // a class whose instances all have a narrow single-body band takes the
+        // streaming kernel (one pass per Heun step, one plane at a time),
+        // exactly as a single context of that size would
+        bool stream = batch_stream_nk_ok(nk, b->elem) && theta_stream_preferred(nk, b->elem);
+        for (int i : kv.second) stream = stream && b->inst[i].band <= kStreamBand;
+        const int P = stream ? 1 : std::max(1, std::min(b->planes[nk], batch_theta_max_planes(nk, b->elem)));
+        wig2_batch::Cls c{nx, nk, (int)thv.size(), 0, (int)av.size(), 0, 4 * b->ncu, 8 * b->ncu, stream};
         if (b->grids.count(kv.first)) {
             c.th_grid = b->grids[kv.first].first;
             c.adv_grid = b->grids[kv.first].second;
@@ -215,15 +221,25 @@ hipError_t class_theta(wig2_batch* b, const wig2_batch::Cls& c, int mode, const 
                                  c.th_count, mode, b->sig_pool, b->kap_pool, c.nk, b->planes[c.nk], grid, st);
 }
 
-// One Strang step of one size class (six launches on one stream).
+// The Heun sub-step of one size class on pool `f` (k1 as stage buffer).
+template <typename T>
+hipError_t class_heun(wig2_batch* b, const wig2_batch::Cls& c, void* f, int grid, hipStream_t st)
+{
+    if (c.stream)
+        return launch_theta_stream_batch<T>((T*)f, b->insts_d, b->th_d + c.th_begin, c.th_count, b->sig_pool,
+                                            b->kap_pool, c.nk, grid, st);
+    hipError_t e = class_theta<T>(b, c, 0, f, nullptr, b->k1, grid, st);
+    return e != hipSuccess ? e : class_theta<T>(b, c, 1, f, b->k1, f, grid, st);
+}
+
+// One Strang step of one size class (five or six launches on one stream).
 template <typename T>
 hipError_t class_step(wig2_batch* b, const wig2_batch::Cls& c, hipStream_t st)
 {
     hipError_t e;
     if ((e = class_advect<T>(b, c, 1, b->f, b->tmp, c.adv_grid, st)) != hipSuccess) return e;
     if ((e = class_advect<T>(b, c, 2, b->tmp, b->f, c.adv_grid, st)) != hipSuccess) return e;
-    if ((e = class_theta<T>(b, c, 0, b->f, nullptr, b->k1, c.th_grid, st)) != hipSuccess) return e;
-    if ((e = class_theta<T>(b, c, 1, b->f, b->k1, b->f, c.th_grid, st)) != hipSuccess) return e;
+    if ((e = class_heun<T>(b, c, b->f, c.th_grid, st)) != hipSuccess) return e;
     if ((e = class_advect<T>(b, c, 1, b->f, b->tmp, c.adv_grid, st)) != hipSuccess) return e;
     return class_advect<T>(b, c, 2, b->tmp, b->f, c.adv_grid, st);
 }
@@ -640,8 +656,7 @@ int wig2_batch_tune(wig2_batch* b, const char* cache_path, int32_t force)
     };
     auto t_th = [&](const wig2_batch::Cls& c, int grid) {
         return time_ms(b, [&] {
-            b->elem == 8 ? class_theta<double>(b, c, 0, b->tmp, nullptr, b->k1, grid, b->st)
-                         : class_theta<float>(b, c, 0, b->tmp, nullptr, b->k1, grid, b->st);
+            b->elem == 8 ? class_heun<double>(b, c, b->tmp, grid, b->st) : class_heun<float>(b, c, b->tmp, grid, b->st);
         }, 2);
     };
     // 1. planes per Theta workgroup per nk, timed over all classes of that nk
@@ -649,6 +664,10 @@ int wig2_batch_tune(wig2_batch* b, const char* cache_path, int32_t force)
     for (auto& c : b->cls)
         if (std::find(nks.begin(), nks.end(), c.nk) == nks.end()) nks.push_back(c.nk);
     for (int nk : nks) {
+        bool stream_nk = false;
+        for (auto& c : b->cls)
+            if (c.nk == nk && c.stream) stream_nk = true;
+        if (stream_nk) continue;  // one plane at a time
         const int maxp = std::max(1, std::min(4, batch_theta_max_planes(nk, b->elem)));
         float best = 1e30f;
         int bp = b->planes[nk];

@@ -207,7 +207,8 @@ hipError_t theta(wig2_ctx* c, const T* u, const T* v, T* out, int mode, double t
 
 bool use_stream(wig2_ctx* c)
 {
-    return c->theta_path != WIG2_THETA_GENERAL && theta_stream_ok(theta_args(c));
+    if (c->theta_path == WIG2_THETA_GENERAL || !theta_stream_ok(theta_args(c))) return false;
+    return c->theta_path == WIG2_THETA_STREAM || theta_stream_preferred(c->g.nk, c->elem);
 }
 
 // Single-operand Theta forms (streaming kernel or, for nk = 256 boxes, the

@@ -84,6 +84,7 @@ hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int 
 //   form 3: out = x + (tau/2)(Theta[x] + Theta[x + tau Theta[x]])  (Heun)
 // out may alias x or y.
 bool theta_stream_ok(const ThetaArgs& a);
+constexpr int kStreamBand = 4;  // widest single-body band the streaming kernel does on the VALU
 template <typename T>
 hipError_t launch_theta_stream(const ThetaArgs& a, const T* x, const T* y, T* out, int form,
                                double tau, hipStream_t st);
@@ -189,6 +190,17 @@ bool batch_nk_ok(int nk);
 // (at most 4, 1024 threads and 160 KB of LDS).
 int batch_theta_max_planes(int nk, int elem_bytes);
 size_t batch_theta_lds(int nk, int np, int elem_bytes);
+
+// Streaming one-pass Heun Theta over the items of one size class, in place on
+// the state pool (instances with band <= kStreamBand, nk accepted by
+// batch_stream_nk_ok; items are processed plane by plane).
+bool batch_stream_nk_ok(int nk, int elem_bytes);
+// Sizes for which the automatic choice takes the streaming kernel.
+bool theta_stream_preferred(int nk, int elem_bytes);
+template <typename T>
+hipError_t launch_theta_stream_batch(T* pool, const BatchInst* insts, const ThItem* items, int nitems,
+                                     const double* sig_pool, const double* kap_pool, int nk, int grid,
+                                     hipStream_t st);
 
 // One persistent launch over the items of one size class (all instances with
 // this nx for the sweep, this nk for Theta).

@@ -34,7 +34,6 @@ namespace wig2 {
 namespace {
 using namespace mf;
 
-constexpr int kStreamBand = 4;  // widest single-body band done on the VALU
 
 template <typename T>
 struct Vec16;
@@ -72,6 +71,195 @@ constexpr int stream_waves_per_eu()
     return (sizeof(T) == 4 && NK == 128 && FORM != 3 && WS == 1) ? 4 : 1;
 }
 
+// Theta work on one plane held in LDS (X, and tk for the pair term), after
+// the barrier that published it: both passes for the one-pass Heun form,
+// one pass and the epilogue otherwise.  Ends with a barrier, after which X
+// may be rewritten.  Every thread of the workgroup calls it.
+template <typename T, int NK, bool TWO, int FORM, int WS>
+__device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl, const double* __restrict__ sig1,
+                                             const double* __restrict__ sig2, int band, double tau, T* X,
+                                             const T* tk, int lane, int w, int J0)
+{
+    typedef typename Acc<T>::V V;
+    typedef StreamLayout<T, NK> L;
+    constexpr int NW = NK / 16;
+    constexpr int NS = NW + 1;
+    constexpr int NSH = (NS + WS - 1) / WS;
+    constexpr int LD = L::LD;
+    const int li = lane & 15, lk = lane >> 4;
+
+    const int i1 = (int)(pl / nx), i2 = (int)(pl % nx);
+    const long pbase = pl * (long)NK * NK;
+
+    // Lane-owned points: accumulator element (jj, q) is the point
+    // n1 = 16w + acc_row(lk, q), n2 = 16(w + j) + li - n1 of skewed tile
+    // j = J0 + jj, when j < NS and 0 <= n2 < NK.
+    // Reads for points outside the plane hit the zero gaps (or clamp) and
+    // their results are not stored.
+    // Position arithmetic restarts from an opaque copy of the lane id in
+    // each loop body, so the compiler cannot hoist the 4*NS per-point
+    // addresses and masks out of the loops and keep them all live.
+    auto opaque_lane = [&]() {
+        int l = lane;
+        asm volatile("" : "+v"(l));
+        return l;
+    };
+    int el = opaque_lane();
+    auto col = [&](int jj, int q) {
+        return 16 * (w + J0 + jj) + (el & 15) - (16 * w + acc_row<T>(el >> 4, q));
+    };
+    auto tile_ok = [&](int jj) { return WS == 1 || J0 + jj < NS; };  // wave-uniform
+    auto row = [&](int q) { return 16 * w + acc_row<T>(el >> 4, q); };
+    auto lds_at = [&](int j, int q) { return X + row(q) * LD + col(j, q); };
+
+    // acc = Theta of the plane held in X, at the lane-owned points
+    auto theta_pass = [&](V (&acc)[NSH]) {
+#pragma unroll
+        for (int j = 0; j < NSH; ++j) acc[j] = V{0, 0, 0, 0};
+        if constexpr (TWO) {
+            // Output tile (row block w, skewed tile j) covers s in
+            // [16(w+j), 16(w+j)+16); the 16 rows k of block KB hold non-zero
+            // H[k][s] = X[k][s - k] for that tile iff 0 <= w + j - KB <= NW.
+            // A = tk[r - k + NK] (r = 16w + li), B = X[k LD + s - k] (zero gaps
+            // outside the plane).
+            const T* pa = tk + 16 * w + li + NK - lk;
+            const T* pb = X + lk * (LD - 1) + 16 * (w + J0) + li;
+#pragma unroll
+            for (int KB = 0; KB < NW; ++KB) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int kb = 4 * KB + i;
+                    const T a = pa[-4 * kb];
+                    // All operand reads are issued before the (scalar)
+                    // tile tests; reads of inactive tiles stay inside the
+                    // LDS allocation (columns -127 .. 255 of rows 0 .. NK-1)
+                    // and are not used.
+                    T bv[NSH];
+#pragma unroll
+                    for (int j = 0; j < NSH; ++j) bv[j] = pb[4 * kb * (LD - 1) + 16 * j];
+#pragma unroll
+                    for (int j = 0; j < NSH; ++j) {
+                        const int d = w + J0 + j - KB;
+                        if (!tile_ok(j) || d < 0 || d > NW) continue;  // wave-uniform
+                        acc[j] = mma(a, bv[j], acc[j]);
+                    }
+                    // the one-pass Heun form also holds h: fewer reads in flight
+                    if constexpr (FORM == 3) __builtin_amdgcn_sched_barrier(0);
+                }
+                // keep the scheduler from hoisting every operand read of
+                // the unrolled loop (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // single-body differences (modes 1..band of x_i1 along n1, of x_i2
+        // along n2), added onto the pair-term accumulators
+        for (int m = 1; m <= band; ++m) {
+            el = opaque_lane();
+            const T s1 = T(sig1[(long)i1 * NK + m]);
+            const T s2 = T(sig2[(long)i2 * NK + m]);
+#pragma unroll
+            for (int j = 0; j < NSH; ++j) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const T* xp = lds_at(j, q);
+                    acc[j][q] += s1 * (xp[-m * LD] - xp[m * LD]) + s2 * (xp[-m] - xp[m]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    };
+
+    V sacc[NSH];
+    theta_pass(sacc);
+
+    if constexpr (FORM == 3) {
+        // Whole Heun step in one pass over the plane: h = f + tau/2 Theta f
+        // stays in registers, g = f + tau Theta f replaces f in LDS, and
+        // the second pass gives f' = h + tau/2 Theta g.
+        V hv[NSH];
+        el = opaque_lane();
+#pragma unroll
+        for (int j = 0; j < NSH; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const T fx = *lds_at(j, q);
+                hv[j][q] = fx + T(0.5 * tau) * sacc[j][q];
+                sacc[j][q] = fx + T(tau) * sacc[j][q];
+            }
+        __syncthreads();  // every wave is done reading f
+        el = opaque_lane();
+#pragma unroll
+        for (int j = 0; j < NSH; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int n2 = col(j, q);
+                if (tile_ok(j) && n2 >= 0 && n2 < NK) *lds_at(j, q) = sacc[j][q];
+            }
+        __syncthreads();
+        theta_pass(sacc);
+        el = opaque_lane();
+#pragma unroll
+        for (int j = 0; j < NSH; ++j) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int n1 = row(q), n2 = col(j, q);
+                if (tile_ok(j) && n2 >= 0 && n2 < NK)
+                    out[pbase + (long)n1 * NK + n2] = hv[j][q] + T(0.5 * tau) * sacc[j][q];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();  // LDS plane is rewritten next
+        return;
+    }
+
+    // epilogue and store; y (form 2) is fetched one group of tiles ahead
+    constexpr int YG = 1;
+    constexpr int NG = (NSH + YG - 1) / YG;
+    T yv[2][YG][4];
+    auto fetch_y = [&](int g, T (&dst)[YG][4]) {
+#pragma unroll
+        for (int jj = 0; jj < YG; ++jj) {
+            const int j = g * YG + jj;
+            if (j >= NSH) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int n1 = row(q);
+                const int c = min(max(col(j, q), 0), NK - 1);
+                dst[jj][q] = y[pbase + (long)n1 * NK + c];
+            }
+        }
+    };
+    el = opaque_lane();
+    if constexpr (FORM == 2) fetch_y(0, yv[0]);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        if constexpr (FORM == 2) {
+            if (g + 1 < NG) fetch_y(g + 1, yv[(g + 1) & 1]);
+        }
+#pragma unroll
+        for (int jj = 0; jj < YG; ++jj) {
+            const int j = g * YG + jj;
+            if (j >= NSH) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int n1 = row(q);
+                const int n2 = col(j, q);
+                const T val = sacc[j][q];
+                T o;
+                if constexpr (FORM == 0)
+                    o = val;
+                else if constexpr (FORM == 1)
+                    o = *lds_at(j, q) + T(tau) * val;
+                else
+                    o = T(0.5) * (yv[g & 1][jj][q] + *lds_at(j, q)) + T(0.5 * tau) * val;
+                if (tile_ok(j) && n2 >= 0 && n2 < NK) out[pbase + (long)n1 * NK + n2] = o;
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();  // LDS plane is rewritten next
+}
+
 // WS waves share each 16-row block (WS = 2: 2 NK/16 waves per workgroup, each
 // with about half of the block's skewed tiles), trading registers per wave
 // for more waves to hide LDS and issue latency behind the matrix cores.
@@ -102,7 +290,6 @@ __global__ __launch_bounds__(NK / 16 * 64 * WS, (stream_waves_per_eu<T, NK, FORM
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (scalar)
     const int w = wv % NW;              // row block
     const int J0 = (wv / NW) * NSH;     // first skewed tile of this wave
-    const int li = lane & 15, lk = lane >> 4;
 
     // zero gaps once; plane writes never touch them
     for (int e = tid; e < L::PADR * LD; e += NT) {
@@ -158,176 +345,7 @@ __global__ __launch_bounds__(NK / 16 * 64 * WS, (stream_waves_per_eu<T, NK, FORM
             if (pl + stride < np) fetch(pl + stride);
         }
 
-        const int i1 = (int)(pl / nx), i2 = (int)(pl % nx);
-        const long pbase = pl * (long)NK * NK;
-
-        // Lane-owned points: accumulator element (jj, q) is the point
-        // n1 = 16w + acc_row(lk, q), n2 = 16(w + j) + li - n1 of skewed tile
-        // j = J0 + jj, when j < NS and 0 <= n2 < NK.
-        // Reads for points outside the plane hit the zero gaps (or clamp) and
-        // their results are not stored.
-        // Position arithmetic restarts from an opaque copy of the lane id in
-        // each loop body, so the compiler cannot hoist the 4*NS per-point
-        // addresses and masks out of the loops and keep them all live.
-        auto opaque_lane = [&]() {
-            int l = lane;
-            asm volatile("" : "+v"(l));
-            return l;
-        };
-        int el = opaque_lane();
-        auto col = [&](int jj, int q) {
-            return 16 * (w + J0 + jj) + (el & 15) - (16 * w + acc_row<T>(el >> 4, q));
-        };
-        auto tile_ok = [&](int jj) { return WS == 1 || J0 + jj < NS; };  // wave-uniform
-        auto row = [&](int q) { return 16 * w + acc_row<T>(el >> 4, q); };
-        auto lds_at = [&](int j, int q) { return X + row(q) * LD + col(j, q); };
-
-        // acc = Theta of the plane held in X, at the lane-owned points
-        auto theta_pass = [&](V (&acc)[NSH]) {
-#pragma unroll
-            for (int j = 0; j < NSH; ++j) acc[j] = V{0, 0, 0, 0};
-            if constexpr (TWO) {
-                // Output tile (row block w, skewed tile j) covers s in
-                // [16(w+j), 16(w+j)+16); the 16 rows k of block KB hold non-zero
-                // H[k][s] = X[k][s - k] for that tile iff 0 <= w + j - KB <= NW.
-                // A = tk[r - k + NK] (r = 16w + li), B = X[k LD + s - k] (zero gaps
-                // outside the plane).
-                const T* pa = tk + 16 * w + li + NK - lk;
-                const T* pb = X + lk * (LD - 1) + 16 * (w + J0) + li;
-#pragma unroll
-                for (int KB = 0; KB < NW; ++KB) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int kb = 4 * KB + i;
-                        const T a = pa[-4 * kb];
-                        // All operand reads are issued before the (scalar)
-                        // tile tests; reads of inactive tiles stay inside the
-                        // LDS allocation (columns -127 .. 255 of rows 0 .. NK-1)
-                        // and are not used.
-                        T bv[NSH];
-#pragma unroll
-                        for (int j = 0; j < NSH; ++j) bv[j] = pb[4 * kb * (LD - 1) + 16 * j];
-#pragma unroll
-                        for (int j = 0; j < NSH; ++j) {
-                            const int d = w + J0 + j - KB;
-                            if (!tile_ok(j) || d < 0 || d > NW) continue;  // wave-uniform
-                            acc[j] = mma(a, bv[j], acc[j]);
-                        }
-                        // the one-pass Heun form also holds h: fewer reads in flight
-                        if constexpr (FORM == 3) __builtin_amdgcn_sched_barrier(0);
-                    }
-                    // keep the scheduler from hoisting every operand read of
-                    // the unrolled loop (register pressure)
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            // single-body differences (modes 1..band of x_i1 along n1, of x_i2
-            // along n2), added onto the pair-term accumulators
-            for (int m = 1; m <= band; ++m) {
-                el = opaque_lane();
-                const T s1 = T(sig1[(long)i1 * NK + m]);
-                const T s2 = T(sig2[(long)i2 * NK + m]);
-#pragma unroll
-                for (int j = 0; j < NSH; ++j) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const T* xp = lds_at(j, q);
-                        acc[j][q] += s1 * (xp[-m * LD] - xp[m * LD]) + s2 * (xp[-m] - xp[m]);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-        };
-
-        V sacc[NSH];
-        theta_pass(sacc);
-
-        if constexpr (FORM == 3) {
-            // Whole Heun step in one pass over the plane: h = f + tau/2 Theta f
-            // stays in registers, g = f + tau Theta f replaces f in LDS, and
-            // the second pass gives f' = h + tau/2 Theta g.
-            V hv[NSH];
-            el = opaque_lane();
-#pragma unroll
-            for (int j = 0; j < NSH; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const T fx = *lds_at(j, q);
-                    hv[j][q] = fx + T(0.5 * tau) * sacc[j][q];
-                    sacc[j][q] = fx + T(tau) * sacc[j][q];
-                }
-            __syncthreads();  // every wave is done reading f
-            el = opaque_lane();
-#pragma unroll
-            for (int j = 0; j < NSH; ++j)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int n2 = col(j, q);
-                    if (tile_ok(j) && n2 >= 0 && n2 < NK) *lds_at(j, q) = sacc[j][q];
-                }
-            __syncthreads();
-            theta_pass(sacc);
-            el = opaque_lane();
-#pragma unroll
-            for (int j = 0; j < NSH; ++j) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int n1 = row(q), n2 = col(j, q);
-                    if (tile_ok(j) && n2 >= 0 && n2 < NK)
-                        out[pbase + (long)n1 * NK + n2] = hv[j][q] + T(0.5 * tau) * sacc[j][q];
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            __syncthreads();  // LDS plane is rewritten next iteration
-            continue;
-        }
-
-        // epilogue and store; y (form 2) is fetched one group of tiles ahead
-        constexpr int YG = 1;
-        constexpr int NG = (NSH + YG - 1) / YG;
-        T yv[2][YG][4];
-        auto fetch_y = [&](int g, T (&dst)[YG][4]) {
-#pragma unroll
-            for (int jj = 0; jj < YG; ++jj) {
-                const int j = g * YG + jj;
-                if (j >= NSH) break;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int n1 = row(q);
-                    const int c = min(max(col(j, q), 0), NK - 1);
-                    dst[jj][q] = y[pbase + (long)n1 * NK + c];
-                }
-            }
-        };
-        el = opaque_lane();
-        if constexpr (FORM == 2) fetch_y(0, yv[0]);
-#pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            if constexpr (FORM == 2) {
-                if (g + 1 < NG) fetch_y(g + 1, yv[(g + 1) & 1]);
-            }
-#pragma unroll
-            for (int jj = 0; jj < YG; ++jj) {
-                const int j = g * YG + jj;
-                if (j >= NSH) break;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int n1 = row(q);
-                    const int n2 = col(j, q);
-                    const T val = sacc[j][q];
-                    T o;
-                    if constexpr (FORM == 0)
-                        o = val;
-                    else if constexpr (FORM == 1)
-                        o = *lds_at(j, q) + T(tau) * val;
-                    else
-                        o = T(0.5) * (yv[g & 1][jj][q] + *lds_at(j, q)) + T(0.5 * tau) * val;
-                    if (tile_ok(j) && n2 >= 0 && n2 < NK) out[pbase + (long)n1 * NK + n2] = o;
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        __syncthreads();  // LDS plane is rewritten next iteration
+        stream_plane<T, NK, TWO, FORM, WS>(y, out, nx, pl, sig1, sig2, band, tau, X, tk, lane, w, J0);
     }
 }
 
@@ -379,6 +397,89 @@ hipError_t go_stream_nk(const ThetaArgs& a, const T* x, const T* y, T* out, int 
                  : go_stream_form<T, NK, false>(a, x, y, out, form, tau, st);
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched ensembles: one persistent launch per size class walks a list of
+// (instance, planes) items and advances each plane by the one-pass Heun form
+// in place (the same per-plane arithmetic as a single context).
+// ---------------------------------------------------------------------------
+template <typename T, int NK>
+__global__ __launch_bounds__(NK / 16 * 64) void k_theta_stream_batch(T* pool, const BatchInst* __restrict__ insts,
+                                                                   const ThItem* __restrict__ items, int nitems,
+                                                                   const double* __restrict__ sig_pool,
+                                                                   const double* __restrict__ kap_pool)
+{
+    typedef typename Vec16<T>::V VT;
+    typedef StreamLayout<T, NK> L;
+    constexpr int NW = NK / 16;
+    constexpr int NT = NW * 64;
+    constexpr int LD = L::LD;
+    constexpr int VN = Vec16<T>::N;
+    constexpr int NV = NK * NK / (NT * VN);
+
+    extern __shared__ unsigned char smem_raw[];
+    T* Xbase = reinterpret_cast<T*>(smem_raw);
+    T* X = Xbase + L::PADR * LD;
+    T* tk = Xbase + L::X_ELEMS;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int e = tid; e < L::PADR * LD; e += NT) {
+        Xbase[e] = T(0);
+        X[NK * LD + e] = T(0);
+    }
+    for (int e = tid; e < NK * kPadCols; e += NT) X[(e / kPadCols) * LD + NK + e % kPadCols] = T(0);
+
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const ThItem item = items[it];
+        const BatchInst I = insts[item.inst];
+        T* base = pool + I.off;
+        const double* sig = sig_pool + I.tab_off;
+        const double* kap = kap_pool + I.tab_off;
+        for (int g = 0; g < item.np; ++g) {
+            const long pl = (long)item.plane0 + g;
+            const VT* src = reinterpret_cast<const VT*>(base + pl * (long)NK * NK);
+            VT xr[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) xr[v] = src[tid + v * NT];
+            double kraw = 0.0;
+            if (I.two_body && tid < 2 * NK) {
+                const int i1 = (int)(pl / I.nx), i2 = (int)(pl % I.nx);
+                const int ell = (i1 - i2 + I.nx) % I.nx;
+                const int d = tid - NK, ad = d < 0 ? -d : d;
+                kraw = kap[(long)ell * NK + min(max(ad, 1), NK - 1)];
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const int e = (tid + v * NT) * VN;
+                *reinterpret_cast<VT*>(X + (e / NK) * LD + e % NK) = xr[v];
+            }
+            if (tid < 2 * NK) {
+                const int d = tid - NK, ad = d < 0 ? -d : d;
+                tk[tid] = (I.two_body && ad > 0 && ad < NK) ? sgnval(d, T(kraw)) : T(0);
+            }
+            __syncthreads();
+            if (I.two_body)
+                stream_plane<T, NK, true, 3, 1>(nullptr, base, I.nx, pl, sig, sig, I.band, I.tau, X, tk, lane, w, 0);
+            else
+                stream_plane<T, NK, false, 3, 1>(nullptr, base, I.nx, pl, sig, sig, I.band, I.tau, X, tk, lane, w,
+                                                 0);
+        }
+    }
+}
+
+template <typename T, int NK>
+hipError_t go_stream_batch(T* pool, const BatchInst* insts, const ThItem* items, int nitems, const double* sig,
+                           const double* kap, int grid, hipStream_t st)
+{
+    auto kf = k_theta_stream_batch<T, NK>;
+    const size_t sm = StreamLayout<T, NK>::bytes;
+    hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kf, dim3(grid), dim3(NK / 16 * 64), sm, st, pool, insts, items, nitems, sig, kap);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 bool theta_stream_ok(const ThetaArgs& a)
@@ -404,6 +505,46 @@ hipError_t launch_theta_stream(const ThetaArgs& a, const T* x, const T* y, T* ou
     default: return hipErrorNotSupported;
     }
 }
+
+bool batch_stream_nk_ok(int nk, int elem_bytes)
+{
+    return nk == 32 || nk == 48 || nk == 64 || nk == 128 || (nk == 96 && elem_bytes == 8);
+}
+
+// Plane sizes where the streaming kernel beats the general one (measured on
+// MI355X, Strang steps of 64^2 x nk^2 and 128^4 with a one-mode V_ext): the
+// one-pass Heun form needs more registers per wave than small planes can
+// afford at the occupancy their LDS footprint would allow.
+bool theta_stream_preferred(int nk, int elem_bytes)
+{
+    if (elem_bytes == 8) return nk == 32 || nk == 64 || nk == 96 || nk == 128;
+    return nk == 128;
+}
+
+template <typename T>
+hipError_t launch_theta_stream_batch(T* pool, const BatchInst* insts, const ThItem* items, int nitems,
+                                     const double* sig_pool, const double* kap_pool, int nk, int grid,
+                                     hipStream_t st)
+{
+    if (nitems == 0) return hipSuccess;
+    if (!batch_stream_nk_ok(nk, sizeof(T))) return hipErrorInvalidValue;
+    switch (nk) {
+    case 32: return go_stream_batch<T, 32>(pool, insts, items, nitems, sig_pool, kap_pool, grid, st);
+    case 48: return go_stream_batch<T, 48>(pool, insts, items, nitems, sig_pool, kap_pool, grid, st);
+    case 64: return go_stream_batch<T, 64>(pool, insts, items, nitems, sig_pool, kap_pool, grid, st);
+    case 96:
+        if constexpr (sizeof(T) == 8)
+            return go_stream_batch<T, 96>(pool, insts, items, nitems, sig_pool, kap_pool, grid, st);
+        else
+            return hipErrorInvalidValue;
+    case 128: return go_stream_batch<T, 128>(pool, insts, items, nitems, sig_pool, kap_pool, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_theta_stream_batch<double>(double*, const BatchInst*, const ThItem*, int, const double*,
+                                                      const double*, int, int, hipStream_t);
+template hipError_t launch_theta_stream_batch<float>(float*, const BatchInst*, const ThItem*, int, const double*,
+                                                     const double*, int, int, hipStream_t);
 
 template hipError_t launch_theta_stream<double>(const ThetaArgs&, const double*, const double*,
                                                 double*, int, double, hipStream_t);

@@ -46,8 +46,10 @@ def _build(precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_batch_equals_single_instances(precision):
     """Every instance of the batch is bitwise the same instance stepped alone
-    with the general Theta kernel (same per-plane and per-line arithmetic,
-    different work distribution)."""
+    (same per-plane and per-line arithmetic, different work distribution):
+    the sizes where the automatic choice is the streaming one-pass Heun
+    kernel (FP64 nk = 32, 64 here) take it in both, the others the general
+    kernel."""
     from paper_2511_11354_amd import wig2
 
     b, pots, states = _build(precision)
@@ -56,7 +58,6 @@ def test_batch_equals_single_instances(precision):
     for i, (nx, nk) in enumerate(SPECS):
         s = wig2.Solver(nx, nk, dt=0.005, precision=precision)
         s.set_potentials(*pots[i])
-        s.set_theta_path("general")
         s.set_state(states[i])
         s.step(4)
         a, c = b.get_state(i), s.get_state()

@@ -3,7 +3,8 @@ pair term from skewed tiles, single-body differences on the vector ALUs)
 against the FP64 oracle and against the general kernel.
 
 It is selected automatically for a torus with a single-body band of at most
-4 modes; these tests also force each kernel explicitly.  The Heun step is
+4 modes at the plane sizes where it is the faster kernel; these tests force
+it at every size it supports, and check the automatic choice.  The Heun step is
 evaluated as g = f + tau Theta f, f' = (f + g)/2 + (tau/2) Theta g, which
 differs from the oracle's f + (tau/2)(Theta f + Theta g) only by rounding.
 """
@@ -33,7 +34,7 @@ POTS = {
 }
 
 
-def solver(nx, nk, pot, two, precision="fp64", scheme="strang", dt=0.01, path="auto"):
+def solver(nx, nk, pot, two, precision="fp64", scheme="strang", dt=0.01, path="stream"):
     from paper_2511_11354_amd import wig2
 
     s = wig2.Solver(nx, nk, dt=dt, scheme=scheme, precision=precision)
@@ -146,3 +147,11 @@ def test_stream_path_selection():
     s3 = wig2.Solver(8, 64, dt=0.01, precision="bf16x2")
     s3.set_potentials(I.cosine(0.5, 20.0), None)
     assert s3.theta_path() == "general"
+    # automatic choice by plane size: FP64 64 and FP32 128 stream, FP32 64 general
+    for prec, nk, want in (("fp64", 64, "stream"), ("fp32", 128, "stream"), ("fp32", 64, "general"),
+                           ("fp64", 48, "general")):
+        s4 = wig2.Solver(4, nk, dt=0.01, precision=prec)
+        s4.set_potentials(I.cosine(0.5, 20.0), I.smoothed_coulomb(1.0, 1.0))
+        assert s4.theta_path() == want, (prec, nk)
+        s4.set_theta_path("stream")
+        assert s4.theta_path() == "stream"
