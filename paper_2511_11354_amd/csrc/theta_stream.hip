@@ -308,10 +308,18 @@ __global__ __launch_bounds__(NK / 16 * 64 * WS, (stream_waves_per_eu<T, NK, FORM
     // wave wait for every load issued before it).
     VT xr[NV];
     double kraw = 0.0;  // kap[l][|d|] of the next plane, d = tid - NK
+    // thread id through an opaque copy: per-element addresses are rebuilt
+    // per plane instead of being hoisted out of the plane loop and kept live
+    auto opaque_tid = [&]() {
+        int t = tid;
+        asm volatile("" : "+v"(t));
+        return t;
+    };
     auto fetch = [&](long p) {
         const VT* src = reinterpret_cast<const VT*>(x + p * (long)NK * NK);
+        const int ot = opaque_tid();
 #pragma unroll
-        for (int v = 0; v < NV; ++v) xr[v] = src[tid + v * NT];
+        for (int v = 0; v < NV; ++v) xr[v] = src[ot + v * NT];
         if constexpr (TWO) {
             if (tid < 2 * NK) {
                 const int i1 = (int)(p / nx), i2 = (int)(p % nx);
@@ -329,9 +337,10 @@ __global__ __launch_bounds__(NK / 16 * 64 * WS, (stream_waves_per_eu<T, NK, FORM
 
     for (; pl < np; pl += stride) {
         if constexpr (!PREFETCH) fetch(pl);
+        const int ot = opaque_tid();
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const int e = (tid + v * NT) * VN;
+            const int e = (ot + v * NT) * VN;
             *reinterpret_cast<VT*>(X + (e / NK) * LD + e % NK) = xr[v];
         }
         if constexpr (TWO) {
