@@ -2,7 +2,9 @@
 //
 // One lane owns one 1-D line along x_dim at fixed (other x, n1, n2).  Lanes of
 // a wavefront take consecutive n2, so every load/store of a wavefront is one
-// contiguous 64-element run (coalesced), whichever dimension is swept.
+// contiguous 64-element run (coalesced), whichever dimension is swept.  The
+// register-resident sweep streams each element through once: its loads and
+// stores carry the non-temporal hint.
 //
 // Spline coefficients: periodic lines solve the circulant system
 // (eta_{i-1} + 4 eta_i + eta_{i+1})/6 = g_i exactly by the factorised
@@ -67,7 +69,7 @@ __device__ __forceinline__ void advect_line_core(const T* __restrict__ in, long 
 {
     T v[NX];
 #pragma unroll
-    for (int i = 0; i < NX; ++i) v[i] = in[ib + (long)i * is];
+    for (int i = 0; i < NX; ++i) v[i] = __builtin_nontemporal_load(&in[ib + (long)i * is]);
 
     T em1 = T(0), eN = T(0);  // box: eta_{-1}, eta_{NX}
     T scale;
@@ -147,7 +149,7 @@ __device__ __forceinline__ void advect_line_core(const T* __restrict__ in, long 
             const double u = (double)i - c;
             if (u < 0.0 || u > (double)(NX - 1)) acc = T(0);
         }
-        out[ob + (long)i * os] = acc;
+        __builtin_nontemporal_store(acc, &out[ob + (long)i * os]);
     }
 }
 
