@@ -90,22 +90,38 @@ def cpu_baseline(w, f0, budget_s=20.0):
     tb = oracle.tables(g, w.vext, w.v12)
     nplanes_all = w.nx * w.nx
     nlines_all = w.nx * w.nk * w.nk
-    npl = max(1, min(nplanes_all, 128))
-    nli = max(1, min(nlines_all, 64 * w.nk * w.nk // 16))
-    t0 = time.perf_counter()
-    oracle.theta_periodic(g, tb["sig_ext"], tb["sig_ext"], tb["vhat12"], f0, True, 0, npl)
-    t_theta = (time.perf_counter() - t0) / npl * nplanes_all
-    t0 = time.perf_counter()
-    oracle.advect(g, 1, 0.5 * w.dt, f0, 0, nli)
-    oracle.advect(g, 2, 0.5 * w.dt, f0, 0, nli)
-    t_sweep = (time.perf_counter() - t0) / (2 * nli) * nlines_all
+
+    def timed(fn, start, count):
+        t0 = time.perf_counter()
+        fn(start, count)
+        return time.perf_counter() - t0
+
+    # one output array for every call, allocated and paged in before any
+    # timing: a full-grid allocation per sampled call would be charged to a
+    # few planes and then scaled up to the whole grid
+    out = np.ones_like(f0)
+    th = lambda p0, n: oracle.theta_periodic(g, tb["sig_ext"], tb["sig_ext"], tb["vhat12"], f0, True,
+                                             p0, n, out=out)
+    sw = lambda l0, n: (oracle.advect(g, 1, 0.5 * w.dt, f0, l0, n, out=out),
+                        oracle.advect(g, 2, 0.5 * w.dt, f0, l0, n, out=out))
+    # a pilot run sizes the sample so that it takes about budget_s in all:
+    # half on Theta planes, half on sweep lines (both directions)
+    p0 = min(nplanes_all, 4)
+    per_plane = timed(th, 0, p0) / p0
+    l0 = min(nlines_all, w.nk * w.nk)
+    per_line = timed(sw, 0, l0) / l0
+    npl = max(1, min(nplanes_all - p0, int(0.5 * budget_s / per_plane)))
+    nli = max(1, min(nlines_all - l0, int(0.5 * budget_s / per_line)))
+    s_theta, s_sweep = timed(th, p0, npl), timed(sw, l0, nli)
+    t_theta = s_theta / npl * nplanes_all
+    t_sweep = s_sweep / (2 * nli) * nlines_all
     t_step = 2 * t_theta + 4 * t_sweep
     return {"value": w.points / t_step, "unit": "point-updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": (f"FP64 oracle on {npl} of {nplanes_all} x-pair planes (Theta) and "
                        f"{nli} of {nlines_all} lines per sweep direction, scaled to one step "
                        f"of 2 Theta + 4 sweeps"),
-            "s_per_step_extrapolated": t_step}
+            "sample_s": s_theta + s_sweep, "s_per_step_extrapolated": t_step}
 
 
 def bench_surrogate(a):

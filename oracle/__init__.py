@@ -185,19 +185,29 @@ def veff_hxc(g: Grid, lam, xc, xc_n0, n_scale, v12_pair, n):
     return v
 
 
-def theta_periodic(g: Grid, sig1, sig2, vh12, f, two_body=True, plane0=0, nplanes=None):
+def _out(f, out):
+    """A caller-supplied output array (written only where the call computes)
+    or a fresh zeroed one."""
+    if out is None:
+        return np.zeros_like(f)
+    if out.shape != f.shape or out.dtype != np.float64 or not out.flags.c_contiguous:
+        raise ValueError("out must be a C-contiguous float64 array of f's shape")
+    return out
+
+
+def theta_periodic(g: Grid, sig1, sig2, vh12, f, two_body=True, plane0=0, nplanes=None, out=None):
     if nplanes is None:
         nplanes = g.nx * g.nx - plane0
-    out = np.zeros_like(f)
+    out = _out(f, out)
     lib().or_theta_periodic(ctypes.byref(g), _p(sig1), _p(sig2), _p(vh12), int(two_body),
                             plane0, nplanes, _p(f), _p(out))
     return out
 
 
-def theta_dense(g: Grid, K1, K2, f, plane0=0, nplanes=None):
+def theta_dense(g: Grid, K1, K2, f, plane0=0, nplanes=None, out=None):
     if nplanes is None:
         nplanes = g.nx * g.nx - plane0
-    out = np.zeros_like(f)
+    out = _out(f, out)
     lib().or_theta_dense(ctypes.byref(g), _p(K1), _p(K2), plane0, nplanes, _p(f), _p(out))
     return out
 
@@ -208,10 +218,10 @@ def sem_kernel(g: Grid, v_x: np.ndarray) -> np.ndarray:
     return K
 
 
-def advect(g: Grid, dim: int, s: float, f: np.ndarray, line0=0, nlines=None) -> np.ndarray:
+def advect(g: Grid, dim: int, s: float, f: np.ndarray, line0=0, nlines=None, out=None) -> np.ndarray:
     if nlines is None:
         nlines = g.nx * g.nk * g.nk - line0
-    out = np.zeros_like(f)
+    out = _out(f, out)
     rc = lib().or_advect(ctypes.byref(g), dim, s, line0, nlines, _p(f), _p(out))
     if rc:
         raise RuntimeError("or_advect failed")
