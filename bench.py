@@ -5,7 +5,8 @@ V12 = 1/sqrt(r^2 + 1), seeded Gaussian-mixture state (seed 0), dt = 0.005,
 Strang step (A/2, Heun on Theta, A/2), FP64.  One JSON line on stdout.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32|bf16x2]
-                    [--workload large|tiny] [--scheme strang|lawson] [--no-cpu]
+                    [--workload large|tiny|box|ensemble|surrogate|accuracy]
+                    [--scheme strang|lawson] [--no-cpu]
 
 A "step" is one full time step over the whole grid (2 Theta applications and
 4 advection sweeps).  The state is resident in HBM before timing starts.
@@ -41,6 +42,8 @@ def theta_flops_per_point(nk: int, band: int) -> float:
 def kernel_model(name, npts, elem, nk, band, precision, dense=False):
     """Algorithmic (bytes, flops) of one launch of a kernel class.  dense: the
     box's SEM operator, two dense nk x nk products per plane (4 nk flops/pt)."""
+    if name == "advect_x1x1":
+        return 2 * elem * npts, 40.0 * npts  # two sweeps, one read and one write
     if name.startswith("advect"):
         return 2 * elem * npts, 20.0 * npts
     fl = (4.0 * nk if dense else theta_flops_per_point(nk, band)) * npts
@@ -194,6 +197,72 @@ def bench_surrogate(a):
     print(json.dumps(out))
 
 
+def bench_accuracy(a):
+    """The reduced-precision forms against the FP64 GPU path on the periodic
+    128^4 workload (mixture seed 0): every form advances the same initial
+    state by the same steps; at checkpoints the one-particle density n1 and
+    the pair density n12 (FP64 reductions) are compared with FP64's, as
+    max|n - n_fp64| / max|n_fp64|, and the mass and energy drift are
+    recorded.  Rates are timed between checkpoints (observables excluded)."""
+    import numpy as np
+    import torch
+
+    from paper_2511_11354_amd import inputs as I
+    from paper_2511_11354_amd import wig2
+
+    w = I.large_periodic(u=1.0)
+    nsteps = a.steps
+    marks = sorted({m for m in (1, 10, 100, nsteps) if m <= nsteps})
+    f0 = None
+    ref = {}
+    forms = {}
+    for prec in ("fp64", "fp32", "bf16x2"):
+        s = wig2.Solver(w.nx, w.nk, x_min=w.x_min, x_max=w.x_max, dt=w.dt, precision=prec)
+        s.set_potentials(w.vext, w.v12)
+        if f0 is None:
+            x, p, _ = s.nodes()
+            f0 = I.mixture(x, p, seed=0, period=w.x_max - w.x_min)
+        s.set_state(f0)
+        ob0 = s.observables()
+        done, secs, rows = 0, 0.0, []
+        for m in marks:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(m - done)
+            torch.cuda.synchronize()
+            secs += time.perf_counter() - t0
+            done = m
+            ob = s.observables()
+            row = {"step": m, "mass_drift": abs(ob["mass"] - ob0["mass"]) / abs(ob0["mass"]),
+                   "energy_drift": abs(ob["energy"] - ob0["energy"]) / abs(ob0["energy"])}
+            if prec == "fp64":
+                ref[m] = (ob["n1"].copy(), ob["n12"].copy(), ob["mass"], ob["energy"])
+            else:
+                n1r, n12r, mr, er = ref[m]
+                row["err_n1"] = float(np.abs(ob["n1"] - n1r).max() / np.abs(n1r).max())
+                row["err_n12"] = float(np.abs(ob["n12"] - n12r).max() / np.abs(n12r).max())
+                row["err_mass"] = abs(ob["mass"] - mr) / abs(mr)
+                row["err_energy"] = abs(ob["energy"] - er) / abs(er)
+            rows.append(row)
+            print(f"accuracy: {prec} step {m} {row}", file=sys.stderr, flush=True)
+        forms[prec] = {"value": w.points * nsteps / secs, "ms_per_step": secs / nsteps * 1e3,
+                       "theta_kernel": s.theta_path(), "checkpoints": rows}
+        s.close()
+        del s
+        torch.cuda.synchronize()
+    out = {
+        "metric": METRIC, "value": forms["fp64"]["value"], "unit": "point-updates/s", "n_gpus": 1,
+        "steps": nsteps, "warmup": 0, "ms_per_step": forms["fp64"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE["fp64"],
+        "data": "synthetic",
+        "config": {"workload": w.name + "-accuracy", "nx": w.nx, "nk": w.nk, "points": w.points,
+                   "dt": w.dt, "scheme": "strang", "V12_U": 1.0, "seed": 0,
+                   "error": "max-abs difference / max-abs FP64 value, per checkpoint"},
+        "forms": forms, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def bench_ensemble(a):
     """64 uneven periodic instances (seeds 1000..1063): one batched step of
     the whole ensemble per 'step', FP32, against a loop over 64 single
@@ -282,10 +351,11 @@ def main():
                     help="default: fp64 for the single-grid workloads, fp32 for the ensemble")
     ap.add_argument("--scheme", default="strang", choices=["strang", "lawson"])
     ap.add_argument("--workload", default="large",
-                    choices=["large", "tiny", "ensemble", "box", "surrogate"],
+                    choices=["large", "tiny", "ensemble", "box", "surrogate", "accuracy"],
                     help="large: periodic 128^4 (default); tiny: periodic 32^4; ensemble: 64 "
                          "uneven periodic instances; box: 129^2 x 256^2 SEM box; surrogate: "
-                         "128^4 FP32 with the learned pair increment")
+                         "128^4 FP32 with the learned pair increment; accuracy: FP32 and "
+                         "split-BF16 against FP64 at 128^4 over --steps steps")
     ap.add_argument("--potential", default="harmonic", choices=["harmonic", "double_well"],
                     help="V_ext of the box workload")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "profiles", "tune_cache.json"),
@@ -311,6 +381,8 @@ def main():
         return bench_ensemble(a)
     if a.workload == "surrogate":
         return bench_surrogate(a)
+    if a.workload == "accuracy":
+        return bench_accuracy(a)
     box = a.workload == "box"
     a.precision = a.precision or ("fp32" if box else "fp64")
     if box:

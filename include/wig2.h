@@ -133,8 +133,21 @@ int wig2_state_buffer(wig2_ctx* ctx, void** f_dev, int32_t* elem_bytes);
 /* Mark the state buffer as initialised after the caller wrote it. */
 int wig2_state_written(wig2_ctx* ctx);
 
-/* Advance nsteps steps of the configured scheme (asynchronous). */
+/* Advance nsteps steps of the configured scheme (asynchronous).
+ * Strang (Sec. 4.1 splitting of the advection from the Theta term): each
+ * step is A(dt/2), Heun on Theta with V_eff frozen, A(dt/2), where the
+ * entering A sweeps x1 then x2 and the leaving A sweeps x2 then x1 (the
+ * sweeps act on different axes and commute).  Within one call the x1
+ * half-sweep that ends a step and the one that begins the next run as one
+ * launch, bitwise equal to nsteps calls of one step each.  Lawson
+ * predictor-corrector (Sec. 4.1): a = A_dt f, b = A_dt Theta[f],
+ * f+ = a + (dt/2) Theta[a + dt b] + (dt/2) b. */
 int wig2_step(wig2_ctx* ctx, int64_t nsteps);
+
+/* Strang only: enable (default) or disable the joint launch of consecutive
+ * x1 half-sweeps within a wig2_step call (results are bitwise the same; for
+ * verification and timing).  0 on success. */
+int wig2_set_sweep_fusion(wig2_ctx* ctx, int32_t enable);
 
 /* Observables of the current state (synchronises).  n1[nx], n12[nx*nx] (x1
  * major), f1[nx*nk] (reduced Wigner function W_red(x1,p1)) may be NULL.
@@ -163,7 +176,8 @@ enum {
     WIG2_PROF_THETA_STAGE2 = 3, /* second Heun stage (both kernels)               */
     WIG2_PROF_MEANFIELD = 4,    /* density moments + mean-field symbols     */
     WIG2_PROF_THETA_HEUN = 5,   /* stream, Strang: both Heun stages in one pass */
-    WIG2_PROF_N = 6
+    WIG2_PROF_ADVECT_X1X1 = 6,  /* Strang: two x1 half-sweeps in one launch     */
+    WIG2_PROF_N = 7
 };
 int wig2_profile(wig2_ctx* ctx, int32_t enable);
 int wig2_profile_read(wig2_ctx* ctx, double* ms, int64_t* counts, int32_t reset);

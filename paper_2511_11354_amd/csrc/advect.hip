@@ -23,17 +23,76 @@
 namespace wig2 {
 namespace {
 
-constexpr int kThomasMax = 1024;
-
-template <typename T>
-__device__ inline void cubic_weights(T t, T& w0, T& w1, T& w2, T& w3)
+__device__ inline void cubic_weights(double t, double (&w)[4])
 {
-    const T s = T(1) - t;
-    const T t2 = t * t, t3 = t2 * t;
-    w0 = s * s * s * T(1.0 / 6.0);
-    w1 = (T(3) * t3 - T(6) * t2 + T(4)) * T(1.0 / 6.0);
-    w2 = (T(-3) * t3 + T(3) * t2 + T(3) * t + T(1)) * T(1.0 / 6.0);
-    w3 = t3 * T(1.0 / 6.0);
+    const double s = 1.0 - t;
+    const double t2 = t * t, t3 = t2 * t;
+    w[0] = s * s * s * (1.0 / 6.0);
+    w[1] = (3.0 * t3 - 6.0 * t2 + 4.0) * (1.0 / 6.0);
+    w[2] = (-3.0 * t3 + 3.0 * t2 + 3.0 * t + 1.0) * (1.0 / 6.0);
+    w[3] = t3 * (1.0 / 6.0);
+}
+
+// Pole of the periodic spline prefilter, as the element type holds it, and
+// the periodic gain 1 / (1 - z1^n) of its start values.
+template <typename T>
+__host__ __device__ constexpr T spline_pole()
+{
+    return T(-2.0 + 1.7320508075688772935274463415059);
+}
+__host__ __device__ constexpr double periodic_gain(double z, int n)
+{
+    double p = 1.0;
+    for (int k = 0; k < n; ++k) p *= z;
+    return 1.0 / (1.0 - p);
+}
+
+// Evaluation taps of one line, out_i = sum_k a_k eta_{i+J+k-1}, from the
+// cubic B-spline weights at t = -c - J, J = floor(-c), times the prefilter
+// scale, in FP64.  The scale (1 - z1)^2 for the periodic prefilter of pole z1
+// (as held in the element type) makes the DC gain of the whole sweep one for
+// that pole (for the exact pole it equals -6 z1).  The tap sum is evaluated
+// in FP64 for FP32 lines too and rounded once at the store: accumulated in
+// float, it shifts the mass of smooth positive lines by a few 1e-9 per sweep,
+// coherently, sweep after sweep.
+struct Taps {
+    double a[4];
+    int J;
+};
+
+template <typename T, bool PER>
+__device__ inline Taps line_taps(double c)
+{
+    Taps tp;
+    const double mc = -c;
+    const double Jd = floor(mc);
+    tp.J = (int)Jd;
+    double w[4];
+    cubic_weights(mc - Jd, w);
+    double scale = 1.0;
+    if constexpr (PER) {
+        const double z1 = (double)spline_pole<T>();
+        scale = (1.0 - z1) * (1.0 - z1);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tp.a[k] = w[k] * scale;
+    return tp;
+}
+
+// Periodic start value of a first-order recursive filter of pole z over a
+// whole period, sum_{k<n} z^k g[(start - dir k) mod n] / (1 - z^n), in FP64
+// by Horner's rule.
+template <typename T, typename G>
+__device__ inline T periodic_start(G g, int n, int start, int dir)
+{
+    const double z = (double)spline_pole<T>();
+    auto at = [&](int k) {
+        int j = (start - dir * k) % n;
+        return (double)g(j < 0 ? j + n : j);
+    };
+    double s = at(n - 1);
+    for (int k = n - 2; k >= 0; --k) s = s * z + at(k);
+    return T(s * periodic_gain(z, n));
 }
 
 struct LineMap {
@@ -62,7 +121,11 @@ __device__ inline LineMap line_map(long line, int nx, int nk, int dim)
 // Register-resident line (NX compile-time): loads, solve and FIR unrolled.
 // Handles displacements |c| <= 1 cell (taps d in [-2, 2]).
 // ---------------------------------------------------------------------------
-template <typename T, int NX, bool PER>
+// PASSES = 2 applies the same sweep twice to the register-resident line
+// (two consecutive half-step sweeps along one dimension): the arithmetic of
+// each pass, and the rounding of the intermediate line to T, are those of two
+// separate launches, without the intermediate round trip through HBM.
+template <typename T, int NX, bool PER, int PASSES = 1>
 __device__ __forceinline__ void advect_line_core(const T* __restrict__ in, long ib, long is,
                                                  T* __restrict__ out, long ob, long os, double c,
                                                  const double* __restrict__ thomas)
@@ -71,100 +134,115 @@ __device__ __forceinline__ void advect_line_core(const T* __restrict__ in, long 
 #pragma unroll
     for (int i = 0; i < NX; ++i) v[i] = __builtin_nontemporal_load(&in[ib + (long)i * is]);
 
-    T em1 = T(0), eN = T(0);  // box: eta_{-1}, eta_{NX}
-    T scale;
-    if constexpr (PER) {
-        const T z1 = T(-2.0 + 1.7320508075688772935274463415059);
-        // causal filter, periodic start value over the full period
-        T zk = T(1), s = T(0);
-#pragma unroll
-        for (int k = 0; k < NX; ++k) {
-            s += zk * v[(NX - k) % NX];
-            zk *= z1;
-        }
-        const T inv = T(1) / (T(1) - zk);
-        v[0] = s * inv;
-#pragma unroll
-        for (int i = 1; i < NX; ++i) v[i] += z1 * v[i - 1];
-        // anti-causal filter, periodic start value
-        zk = T(1);
-        s = T(0);
-#pragma unroll
-        for (int k = 0; k < NX; ++k) {
-            s += zk * v[(NX - 1 + k) % NX];
-            zk *= z1;
-        }
-        v[NX - 1] = s * inv;
-#pragma unroll
-        for (int i = NX - 2; i >= 0; --i) v[i] += z1 * v[i + 1];
-        scale = T(-6) * z1;  // eta = scale * v
-    } else {
-        // natural ends: eta_0 = g_0, eta_{N-1} = g_{N-1}; interior Thomas
-        const T e0 = v[0], eL = v[NX - 1];
-        T dprev = T(0);
-#pragma unroll
-        for (int i = 1; i <= NX - 2; ++i) {
-            T rhs = T(6) * v[i] - dprev;
-            if (i == 1) rhs -= e0;
-            if (i == NX - 2) rhs -= eL;
-            dprev = rhs * T(thomas[i]);
-            v[i] = dprev;
-        }
-#pragma unroll
-        for (int i = NX - 3; i >= 1; --i) v[i] -= T(thomas[i]) * v[i + 1];
-        em1 = T(2) * v[0] - v[1];
-        eN = T(2) * v[NX - 1] - v[NX - 2];
-        scale = T(1);
-    }
-
-    // taps: out_i = sum_d a_d eta_{i+d}, d in [-2, 2]; J = floor(-c), t = -c - J
-    const double mc = -c;
-    const double Jd = floor(mc);
-    const int J = (int)Jd;
-    T w0, w1, w2, w3;
-    cubic_weights(T(mc - Jd), w0, w1, w2, w3);
-    T a[5];
+    // c as one rounded value: the taps and the box mask both start from it
+    // (no contraction of its product into later arithmetic), so every pass
+    // and every launch derives the same taps from it
+    asm volatile("" : "+v"(c));
+    const Taps tp = line_taps<T, PER>(c);
+    // the same taps on the 5-point window d in [-2, 2] around i (|c| <= 1:
+    // J in {-1, 0, 1}, and the weight that would fall at d = 3 is zero)
+    double ad[5];
 #pragma unroll
     for (int d = -2; d <= 2; ++d) {
-        const int k = d - J + 1;
-        T ad = (k == 0) ? w0 : (k == 1) ? w1 : (k == 2) ? w2 : (k == 3) ? w3 : T(0);
-        a[d + 2] = ad * scale;
+        const int k = d - tp.J + 1;
+        ad[d + 2] = (k == 0) ? tp.a[0] : (k == 1) ? tp.a[1] : (k == 2) ? tp.a[2] : (k == 3) ? tp.a[3] : 0.0;
     }
+
 #pragma unroll
-    for (int i = 0; i < NX; ++i) {
-        T acc = T(0);
+    for (int pass = 0; pass < PASSES; ++pass) {
+        T em1 = T(0), eN = T(0);  // box: eta_{-1}, eta_{NX}
+        if constexpr (PER) {
+            constexpr T z1 = spline_pole<T>();
+            constexpr double z1d = (double)z1;
+            constexpr double inv = periodic_gain(z1d, NX);
+            // Periodic start values, sum_k z1^k g[j_k] / (1 - z1^NX), in FP64
+            // by Horner's rule.  FP64 lines sum the whole period; FP32 lines
+            // stop after KS terms, where |z1|^KS < 2e-14 of the first term
+            // (far below a float's rounding: the sum is exact in FP32).
+            constexpr int KS = sizeof(T) == 4 && NX > 24 ? 24 : NX;
+            // causal filter: j_k = -k mod NX
+            double s = (double)v[(NX - (KS - 1)) % NX];
 #pragma unroll
-        for (int d = -2; d <= 2; ++d) {
-            T e;
-            if constexpr (PER) {
-                e = v[(i + d + NX) % NX];
-            } else {
-                const int j = i + d;
-                e = (j >= 0 && j < NX) ? v[j < 0 ? 0 : (j >= NX ? NX - 1 : j)]
-                                       : (j == -1 ? em1 : (j == NX ? eN : T(0)));
+            for (int k = KS - 2; k >= 0; --k) s = s * z1d + (double)v[(NX - k) % NX];
+            v[0] = T(s * inv);
+#pragma unroll
+            for (int i = 1; i < NX; ++i) v[i] += z1 * v[i - 1];
+            // anti-causal filter: j_k = NX - 1 + k mod NX
+            s = (double)v[(NX - 1 + KS - 1) % NX];
+#pragma unroll
+            for (int k = KS - 2; k >= 0; --k) s = s * z1d + (double)v[(NX - 1 + k) % NX];
+            v[NX - 1] = T(s * inv);
+#pragma unroll
+            for (int i = NX - 2; i >= 0; --i) v[i] += z1 * v[i + 1];
+            // eta = (1 - z1)^2 v; the factor sits in the taps
+        } else {
+            // natural ends: eta_0 = g_0, eta_{N-1} = g_{N-1}; interior Thomas
+            const T e0 = v[0], eL = v[NX - 1];
+            T dprev = T(0);
+#pragma unroll
+            for (int i = 1; i <= NX - 2; ++i) {
+                T rhs = T(6) * v[i] - dprev;
+                if (i == 1) rhs -= e0;
+                if (i == NX - 2) rhs -= eL;
+                dprev = rhs * T(thomas[i]);
+                v[i] = dprev;
             }
-            acc += a[d + 2] * e;
+#pragma unroll
+            for (int i = NX - 3; i >= 1; --i) v[i] -= T(thomas[i]) * v[i + 1];
+            em1 = T(2) * v[0] - v[1];
+            eN = T(2) * v[NX - 1] - v[NX - 2];
         }
-        if constexpr (!PER) {
-            const double u = (double)i - c;
-            if (u < 0.0 || u > (double)(NX - 1)) acc = T(0);
+
+        T r[NX];  // the line after a pass that is not the last (unused when PASSES = 1)
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            double acc = 0.0;
+#pragma unroll
+            for (int d = -2; d <= 2; ++d) {
+                T e;
+                if constexpr (PER) {
+                    e = v[(i + d + NX) % NX];
+                } else {
+                    const int j = i + d;
+                    e = (j >= 0 && j < NX) ? v[j < 0 ? 0 : (j >= NX ? NX - 1 : j)]
+                                           : (j == -1 ? em1 : (j == NX ? eN : T(0)));
+                }
+                acc += ad[d + 2] * (double)e;
+            }
+            T o = T(acc);
+            if constexpr (!PER) {
+                const double u = (double)i - c;
+                if (u < 0.0 || u > (double)(NX - 1)) o = T(0);
+            }
+            if (pass + 1 < PASSES)
+                r[i] = o;
+            else
+                __builtin_nontemporal_store(o, &out[ob + (long)i * os]);
         }
-        __builtin_nontemporal_store(acc, &out[ob + (long)i * os]);
+        if (pass + 1 < PASSES) {
+            // the next pass takes the line as opaque values, as a separate
+            // launch takes it from memory: no algebra across the passes
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                v[i] = r[i];
+                asm volatile("" : "+v"(v[i]));
+            }
+        }
     }
 }
 
-template <typename T, int NX, bool PER>
+template <typename T, int NX, bool PER, int PASSES = 1>
 __device__ __forceinline__ void advect_line_reg(const T* __restrict__ in, T* __restrict__ out,
                                                 int nk, int dim, long line, double cpp,
                                                 const double* __restrict__ pn,
                                                 const double* __restrict__ thomas)
 {
     const LineMap lm = line_map(line, NX, nk, dim);
-    advect_line_core<T, NX, PER>(in, lm.base, lm.stride, out, lm.base, lm.stride, cpp * pn[lm.nv],
-                                 thomas);
+    advect_line_core<T, NX, PER, PASSES>(in, lm.base, lm.stride, out, lm.base, lm.stride,
+                                         cpp * pn[lm.nv], thomas);
 }
 
-template <typename T, int NX, bool PER>
+template <typename T, int NX, bool PER, int PASSES>
 __global__ __launch_bounds__(64) void k_advect_reg(const T* __restrict__ in, T* __restrict__ out,
                                                    int nk, int dim, long nlines, double cpp,
                                                    const double* __restrict__ pn,
@@ -172,7 +250,7 @@ __global__ __launch_bounds__(64) void k_advect_reg(const T* __restrict__ in, T* 
 {
     const long line = (long)blockIdx.x * 64 + threadIdx.x;
     if (line >= nlines) return;
-    advect_line_reg<T, NX, PER>(in, out, nk, dim, line, cpp, pn, thomas);
+    advect_line_reg<T, NX, PER, PASSES>(in, out, nk, dim, line, cpp, pn, thomas);
 }
 
 // ---------------------------------------------------------------------------
@@ -189,37 +267,25 @@ __global__ __launch_bounds__(64) void k_advect_any(const T* __restrict__ in, T* 
     const long line = (long)blockIdx.x * 64 + threadIdx.x;
     if (line >= nlines) return;
     const LineMap lm = line_map(line, nx, nk, dim);
-    const double c = cpp * pn[lm.nv];
+    double c = cpp * pn[lm.nv];
+    asm volatile("" : "+v"(c));
     auto G = [&](int i) { return in[lm.base + (long)i * lm.stride]; };
     auto E = [&](int i) -> T& { return ws[lm.base + (long)i * lm.stride]; };
-    T em1 = T(0), eN = T(0), scale;
+    T em1 = T(0), eN = T(0);
     if constexpr (PER) {
-        const T z1 = T(-2.0 + 1.7320508075688772935274463415059);
-        T zk = T(1), s = T(0);
-        for (int k = 0; k < nx; ++k) {
-            s += zk * G((nx - k) % nx);
-            zk *= z1;
-        }
-        const T inv = T(1) / (T(1) - zk);
-        T prev = s * inv;
+        const T z1 = spline_pole<T>();
+        T prev = periodic_start<T>(G, nx, 0, 1);
         E(0) = prev;
         for (int i = 1; i < nx; ++i) {
             prev = G(i) + z1 * prev;
             E(i) = prev;
         }
-        zk = T(1);
-        s = T(0);
-        for (int k = 0; k < nx; ++k) {
-            s += zk * E((nx - 1 + k) % nx);
-            zk *= z1;
-        }
-        prev = s * inv;
+        prev = periodic_start<T>([&](int j) { return E(j); }, nx, nx - 1, -1);
         E(nx - 1) = prev;
         for (int i = nx - 2; i >= 0; --i) {
             prev = E(i) + z1 * prev;
             E(i) = prev;
         }
-        scale = T(-6) * z1;
     } else {
         const T e0 = G(0), eL = G(nx - 1);
         E(0) = e0;
@@ -235,34 +301,26 @@ __global__ __launch_bounds__(64) void k_advect_any(const T* __restrict__ in, T* 
         for (int i = nx - 3; i >= 1; --i) E(i) = E(i) - T(thomas[i]) * E(i + 1);
         em1 = T(2) * E(0) - E(1);
         eN = T(2) * E(nx - 1) - E(nx - 2);
-        scale = T(1);
     }
-    const double mc = -c;
-    const double Jd = floor(mc);
-    const long J = (long)Jd;
-    T w[4];
-    cubic_weights(T(mc - Jd), w[0], w[1], w[2], w[3]);
+    const Taps tp = line_taps<T, PER>(c);
+    const long J = tp.J;
     for (int i = 0; i < nx; ++i) {
-        T acc = T(0);
-        if constexpr (PER) {
+        double acc = 0.0;
+        if (PER || ((double)i - c >= 0.0 && (double)i - c <= (double)(nx - 1))) {
             for (int k = 0; k < 4; ++k) {
-                long j = ((long)i + J + k - 1) % nx;
-                if (j < 0) j += nx;
-                acc += w[k] * E((int)j);
-            }
-            acc *= scale;
-        } else {
-            const double u = (double)i - c;
-            if (u >= 0.0 && u <= (double)(nx - 1)) {
-                for (int k = 0; k < 4; ++k) {
-                    const long j = (long)i + J + k - 1;
-                    T e = (j >= 0 && j < nx) ? E((int)j)
-                                             : (j == -1 ? em1 : (j == nx ? eN : T(0)));
-                    acc += w[k] * e;
+                long j = (long)i + J + k - 1;
+                T e;
+                if constexpr (PER) {
+                    j %= nx;
+                    if (j < 0) j += nx;
+                    e = E((int)j);
+                } else {
+                    e = (j >= 0 && j < nx) ? E((int)j) : (j == -1 ? em1 : (j == nx ? eN : T(0)));
                 }
+                acc += tp.a[k] * (double)e;
             }
         }
-        out[lm.base + (long)i * lm.stride] = acc;
+        out[lm.base + (long)i * lm.stride] = T(acc);
     }
 }
 
@@ -292,11 +350,15 @@ __global__ __launch_bounds__(256) void k_advect_batch(const T* __restrict__ in_p
 
 template <typename T, int NX, bool PER>
 hipError_t run_reg(const T* in, T* out, int nk, int dim, long nl, double cpp, const double* p,
-                   const double* th, hipStream_t st)
+                   const double* th, int passes, hipStream_t st)
 {
     const unsigned nb = (unsigned)((nl + 63) / 64);
-    hipLaunchKernelGGL((k_advect_reg<T, NX, PER>), dim3(nb), dim3(64), 0, st, in, out, nk, dim,
-                       nl, cpp, p, th);
+    if (passes == 2)
+        hipLaunchKernelGGL((k_advect_reg<T, NX, PER, 2>), dim3(nb), dim3(64), 0, st, in, out, nk,
+                           dim, nl, cpp, p, th);
+    else
+        hipLaunchKernelGGL((k_advect_reg<T, NX, PER, 1>), dim3(nb), dim3(64), 0, st, in, out, nk,
+                           dim, nl, cpp, p, th);
     return hipGetLastError();
 }
 
@@ -346,26 +408,28 @@ bool advect_in_registers(int nx, bool periodic, double max_cells)
 template <typename T>
 hipError_t launch_advect(const T* in, T* out, T* work, int nx, int nk, int dim, bool periodic,
                          double cpp, double max_cells, const double* p_dev,
-                         const double* thomas_dev, hipStream_t st)
+                         const double* thomas_dev, hipStream_t st, int passes)
 {
     const long nl = (long)nx * nk * nk;
     if (nl == 0) return hipSuccess;
+    if (passes != 1 && !(passes == 2 && advect_in_registers(nx, periodic, max_cells)))
+        return hipErrorInvalidValue;
     if (advect_in_registers(nx, periodic, max_cells)) {
         if (periodic) {
             switch (nx) {
-            case 16: return run_reg<T, 16, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
-            case 32: return run_reg<T, 32, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
-            case 48: return run_reg<T, 48, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
-            case 64: return run_reg<T, 64, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
-            case 96: return run_reg<T, 96, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
-            case 128: return run_reg<T, 128, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
+            case 16: return run_reg<T, 16, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
+            case 32: return run_reg<T, 32, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
+            case 48: return run_reg<T, 48, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
+            case 64: return run_reg<T, 64, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
+            case 96: return run_reg<T, 96, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
+            case 128: return run_reg<T, 128, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
             default: break;
             }
         } else {
             switch (nx) {
-            case 33: return run_reg<T, 33, false>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
-            case 65: return run_reg<T, 65, false>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
-            case 129: return run_reg<T, 129, false>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, st);
+            case 33: return run_reg<T, 33, false>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
+            case 65: return run_reg<T, 65, false>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
+            case 129: return run_reg<T, 129, false>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
             default: break;
             }
         }
@@ -383,8 +447,8 @@ hipError_t launch_advect(const T* in, T* out, T* work, int nx, int nk, int dim, 
 
 template hipError_t launch_advect<double>(const double*, double*, double*, int, int, int, bool,
                                           double, double, const double*, const double*,
-                                          hipStream_t);
+                                          hipStream_t, int);
 template hipError_t launch_advect<float>(const float*, float*, float*, int, int, int, bool, double,
-                                         double, const double*, const double*, hipStream_t);
+                                         double, const double*, const double*, hipStream_t, int);
 
 }  // namespace wig2

@@ -232,7 +232,9 @@ hipError_t class_heun(wig2_batch* b, const wig2_batch::Cls& c, void* f, int grid
     return e != hipSuccess ? e : class_theta<T>(b, c, 1, f, b->k1, f, grid, st);
 }
 
-// One Strang step of one size class (five or six launches on one stream).
+// One Strang step of one size class (five or six launches on one stream):
+// half-step sweeps x1 then x2, Heun, half-step sweeps x2 then x1 (the sweep
+// order of a single context's step).
 template <typename T>
 hipError_t class_step(wig2_batch* b, const wig2_batch::Cls& c, hipStream_t st)
 {
@@ -240,8 +242,8 @@ hipError_t class_step(wig2_batch* b, const wig2_batch::Cls& c, hipStream_t st)
     if ((e = class_advect<T>(b, c, 1, b->f, b->tmp, c.adv_grid, st)) != hipSuccess) return e;
     if ((e = class_advect<T>(b, c, 2, b->tmp, b->f, c.adv_grid, st)) != hipSuccess) return e;
     if ((e = class_heun<T>(b, c, b->f, c.th_grid, st)) != hipSuccess) return e;
-    if ((e = class_advect<T>(b, c, 1, b->f, b->tmp, c.adv_grid, st)) != hipSuccess) return e;
-    return class_advect<T>(b, c, 2, b->tmp, b->f, c.adv_grid, st);
+    if ((e = class_advect<T>(b, c, 2, b->f, b->tmp, c.adv_grid, st)) != hipSuccess) return e;
+    return class_advect<T>(b, c, 1, b->tmp, b->f, c.adv_grid, st);
 }
 
 // The whole step: one chain per class, forked from and joined back to the

@@ -35,6 +35,7 @@ struct wig2_ctx {
     int band = 0;
     int theta_path = WIG2_THETA_AUTO;
     bool two_body = false, meanfield = false;
+    bool fuse_sweeps = true;  // Strang: consecutive x1 half-sweeps in one launch
     std::vector<double> x, p, w, vext_x, v12pair;
     double pmax = 0.0;
     bool has_state = false, has_pot = false;
@@ -236,17 +237,19 @@ hipError_t update_meanfield(wig2_ctx* c, const T* a, const T* b, double tau_b)
                             c->st);
 }
 
+// One step of the Lawson predictor-corrector (Sec. 4.1):
+// a = A_tau f, b = A_tau Theta[f], f+ = a + (tau/2) Theta[a + tau b] + (tau/2) b.
 template <typename T>
-hipError_t step_once(wig2_ctx* c)
+hipError_t step_lawson(wig2_ctx* c)
 {
     T* f = static_cast<T*>(c->f);
     T* k1 = static_cast<T*>(c->k1);
     T* tmp = static_cast<T*>(c->tmp);
     const double tau = c->prm.dt;
     hipError_t e;
-#define STEPCHK(x)                  \
-    do {                            \
-        e = (x);                    \
+#define STEPCHK(x)                     \
+    do {                               \
+        e = (x);                       \
         if (e != hipSuccess) return e; \
     } while (0)
     auto ADV = [&](int dim, double sh, const T* in, T* out) {
@@ -261,60 +264,128 @@ hipError_t step_once(wig2_ctx* c)
         return timed(c, WIG2_PROF_MEANFIELD, [&] { return update_meanfield<T>(c, a, b, tb); });
     };
     auto THS = [&](const T* x, const T* y, T* out, int form) {
-        return timed(c, form == 3 ? WIG2_PROF_THETA_HEUN
-                                  : form == 1 ? WIG2_PROF_THETA_STAGE1 : WIG2_PROF_THETA_STAGE2,
+        return timed(c, form == 1 ? WIG2_PROF_THETA_STAGE1 : WIG2_PROF_THETA_STAGE2,
                      [&] { return theta_form<T>(c, x, y, out, form, tau); });
     };
     if (use_forms(c)) {
-        // Heun as g = f + tau Theta f, then (f + g)/2 + (tau/2) Theta g.
-        // Lawson: A_tau g = a + tau b, so its corrector is the same second form
-        // with x = A_tau g and y = a = A_tau f.
-        if (c->prm.scheme == WIG2_STRANG) {
-            STEPCHK(ADV(1, 0.5 * tau, f, tmp));
-            STEPCHK(ADV(2, 0.5 * tau, tmp, f));
-            if (c->meanfield) STEPCHK(MF(f, nullptr, 0.0));
-            if (use_stream(c)) {
-                STEPCHK(THS(f, nullptr, f, 3));
-            } else {
-                STEPCHK(THS(f, nullptr, k1, 1));
-                STEPCHK(THS(k1, f, f, 2));
-            }
-            STEPCHK(ADV(1, 0.5 * tau, f, tmp));
-            STEPCHK(ADV(2, 0.5 * tau, tmp, f));
-        } else {
-            if (c->meanfield) STEPCHK(MF(f, nullptr, 0.0));
-            STEPCHK(THS(f, nullptr, k1, 1));
-            STEPCHK(ADV(1, tau, f, tmp));
-            STEPCHK(ADV(2, tau, tmp, f));
-            STEPCHK(ADV(1, tau, k1, tmp));
-            STEPCHK(ADV(2, tau, tmp, k1));
-            if (c->meanfield) STEPCHK(MF(k1, nullptr, 0.0));
-            STEPCHK(THS(k1, f, f, 2));
-        }
-        return hipSuccess;
-    }
-    if (c->prm.scheme == WIG2_STRANG) {
-        STEPCHK(ADV(1, 0.5 * tau, f, tmp));
-        STEPCHK(ADV(2, 0.5 * tau, tmp, f));
+        // A_tau g = a + tau b for g = f + tau Theta f, so the corrector is
+        // (y + x)/2 + (tau/2) Theta x with x = A_tau g and y = a = A_tau f
         if (c->meanfield) STEPCHK(MF(f, nullptr, 0.0));
-        STEPCHK(TH(f, nullptr, k1, 0));
-        STEPCHK(TH(f, k1, f, 1));
-        STEPCHK(ADV(1, 0.5 * tau, f, tmp));
-        STEPCHK(ADV(2, 0.5 * tau, tmp, f));
-    } else {
-        if (c->meanfield) STEPCHK(MF(f, nullptr, 0.0));
-        STEPCHK(TH(f, nullptr, k1, 0));
+        STEPCHK(THS(f, nullptr, k1, 1));
         STEPCHK(ADV(1, tau, f, tmp));
         STEPCHK(ADV(2, tau, tmp, f));
         STEPCHK(ADV(1, tau, k1, tmp));
         STEPCHK(ADV(2, tau, tmp, k1));
-        if (c->meanfield) STEPCHK(MF(f, k1, tau));
-        STEPCHK(TH(f, k1, f, 1));
+        if (c->meanfield) STEPCHK(MF(k1, nullptr, 0.0));
+        STEPCHK(THS(k1, f, f, 2));
+        return hipSuccess;
     }
+    if (c->meanfield) STEPCHK(MF(f, nullptr, 0.0));
+    STEPCHK(TH(f, nullptr, k1, 0));
+    STEPCHK(ADV(1, tau, f, tmp));
+    STEPCHK(ADV(2, tau, tmp, f));
+    STEPCHK(ADV(1, tau, k1, tmp));
+    STEPCHK(ADV(2, tau, tmp, k1));
+    if (c->meanfield) STEPCHK(MF(f, k1, tau));
+    STEPCHK(TH(f, k1, f, 1));
 #undef STEPCHK
     return hipSuccess;
 }
 
+
+// Heun on Theta (V_eff frozen) from x into out (out may equal x); k1 is free.
+template <typename T>
+hipError_t heun_theta(wig2_ctx* c, T* x, T* out)
+{
+    T* k1 = static_cast<T*>(c->k1);
+    const double tau = c->prm.dt;
+    hipError_t e;
+    if (c->meanfield) {
+        e = timed(c, WIG2_PROF_MEANFIELD, [&] { return update_meanfield<T>(c, x, nullptr, 0.0); });
+        if (e != hipSuccess) return e;
+    }
+    auto THS = [&](const T* a, const T* b, T* o, int form) {
+        return timed(c, form == 3 ? WIG2_PROF_THETA_HEUN
+                                  : form == 1 ? WIG2_PROF_THETA_STAGE1 : WIG2_PROF_THETA_STAGE2,
+                     [&] { return theta_form<T>(c, a, b, o, form, tau); });
+    };
+    auto TH = [&](const T* u, const T* v, T* o, int mode) {
+        return timed(c, mode == 0 ? WIG2_PROF_THETA_STAGE1 : WIG2_PROF_THETA_STAGE2,
+                     [&] { return theta<T>(c, u, v, o, mode, tau); });
+    };
+    if (use_stream(c)) return THS(x, nullptr, out, 3);
+    if (use_forms(c)) {
+        if ((e = THS(x, nullptr, k1, 1)) != hipSuccess) return e;
+        return THS(k1, x, out, 2);
+    }
+    if ((e = TH(x, nullptr, k1, 0)) != hipSuccess) return e;
+    return TH(x, k1, out, 1);
+}
+
+// n >= 1 Strang steps A(tau/2) Heun A(tau/2) with A = (x2 sweep)(x1 sweep)
+// on the way in and A = (x1 sweep)(x2 sweep) on the way out: the sweeps act
+// on different axes with tensor-product operators, so the two orders are the
+// same map (up to rounding).  The x1 half-sweep that ends a step and the one
+// that begins the next are then consecutive and, where the line fits in
+// registers, run as one two-pass launch (the same arithmetic without the
+// intermediate HBM round trip): 3n + 1 state sweeps instead of 4n.  The state
+// ends in c->f.
+template <typename T>
+hipError_t strang_steps(wig2_ctx* c, int64_t n)
+{
+    const double h = 0.5 * c->prm.dt;
+    T* a = static_cast<T*>(c->f);
+    T* b = static_cast<T*>(c->tmp);
+    const double cpp = h / (c->g.mass * c->g.dx());
+    const bool joint = c->fuse_sweeps && advect_in_registers(c->g.nx, c->g.periodic != 0, std::fabs(cpp) * c->pmax);
+    auto sweep = [&](int dim, int passes, const T* in, T* out) {
+        const int cls = passes == 2 ? WIG2_PROF_ADVECT_X1X1 : dim == 1 ? WIG2_PROF_ADVECT_X1 : WIG2_PROF_ADVECT_X2;
+        return timed(c, cls, [&] {
+            return launch_advect<T>(in, out, static_cast<T*>(c->work), c->g.nx, c->g.nk, dim, c->g.periodic != 0,
+                                    cpp, std::fabs(cpp) * c->pmax, c->p_d, c->thomas_d, c->st, passes);
+        });
+    };
+    // one sweep (or two along x1) from a into b, then b holds the state;
+    // two x1 sweeps without the joint launch go through k1
+    auto ADV = [&](int dim, int passes) {
+        hipError_t e;
+        if (passes == 2 && !joint) {
+            T* k1 = static_cast<T*>(c->k1);
+            if ((e = sweep(dim, 1, a, k1)) == hipSuccess) e = sweep(dim, 1, k1, b);
+        } else {
+            e = sweep(dim, passes, a, b);
+        }
+        std::swap(a, b);
+        return e;
+    };
+    // 3n + 1 out-of-place sweeps; for even n the first Heun also writes the
+    // other buffer so that the last sweep lands in c->f
+    const bool flip = n % 2 == 0;
+    hipError_t e;
+    if ((e = ADV(1, 1)) != hipSuccess) return e;
+    for (int64_t k = 0; k < n; ++k) {
+        if ((e = ADV(2, 1)) != hipSuccess) return e;
+        if (k == 0 && flip) {
+            if ((e = heun_theta<T>(c, a, b)) != hipSuccess) return e;
+            std::swap(a, b);
+        } else if ((e = heun_theta<T>(c, a, a)) != hipSuccess) {
+            return e;
+        }
+        if ((e = ADV(2, 1)) != hipSuccess) return e;
+        if ((e = ADV(1, k + 1 < n ? 2 : 1)) != hipSuccess) return e;
+    }
+    return a == static_cast<T*>(c->f) ? hipSuccess : hipErrorUnknown;
+}
+
+template <typename T>
+hipError_t run_steps(wig2_ctx* c, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    if (c->prm.scheme == WIG2_STRANG) return strang_steps<T>(c, n);
+    hipError_t e = hipSuccess;
+    for (int64_t k = 0; k < n && e == hipSuccess; ++k) e = step_lawson<T>(c);
+    return e;
+}
 
 // ---- surrogate blocks -------------------------------------------------------
 
@@ -324,8 +395,7 @@ template <typename T>
 hipError_t run_steps(wig2_ctx* c, int n, bool no_pair)
 {
     c->no_pair = no_pair;
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < n && e == hipSuccess; ++k) e = step_once<T>(c);
+    hipError_t e = run_steps<T>(c, (int64_t)n);
     c->no_pair = false;
     return e;
 }
@@ -778,13 +848,12 @@ int wig2_step(wig2_ctx* c, int64_t n)
         for (; n >= B; n -= B)
             if (int r = c->elem == 8 ? sur_block<double>(c) : sur_block<float>(c)) return r;
     }
-    for (int64_t k = 0; k < n; ++k) {
-        hipError_t e = c->elem == 8 ? step_once<double>(c) : step_once<float>(c);
-        if (e != hipSuccess) return fail(c, e == hipErrorNotSupported ? WIG2_ENOTSUP : WIG2_EDEVICE,
-                                         std::string("step: ") + hipGetErrorString(e));
-        c->nstep++;
-        c->t += c->prm.dt;
-    }
+    if (n == 0) return WIG2_OK;
+    hipError_t e = c->elem == 8 ? run_steps<double>(c, n) : run_steps<float>(c, n);
+    if (e != hipSuccess) return fail(c, e == hipErrorNotSupported ? WIG2_ENOTSUP : WIG2_EDEVICE,
+                                     std::string("step: ") + hipGetErrorString(e));
+    c->nstep += n;
+    c->t += (double)n * c->prm.dt;
     return WIG2_OK;
 }
 
@@ -820,6 +889,13 @@ int wig2_advect(wig2_ctx* c, int32_t dim, double s, const void* in, void* out)
     hipError_t e = c->elem == 8 ? advect<double>(c, dim, s, (const double*)in, (double*)out)
                                 : advect<float>(c, dim, s, (const float*)in, (float*)out);
     if (e != hipSuccess) return fail(c, WIG2_EDEVICE, std::string("advect: ") + hipGetErrorString(e));
+    return WIG2_OK;
+}
+
+int wig2_set_sweep_fusion(wig2_ctx* c, int32_t enable)
+{
+    if (!c) return WIG2_EINVAL;
+    c->fuse_sweeps = enable != 0;
     return WIG2_OK;
 }
 

@@ -47,13 +47,15 @@ double host_entropy(const GridInfo& g, const std::vector<double>& f1, std::vecto
 // cells_per_p = s / (m dx); p_dev[nk] momentum nodes; work: state-sized scratch
 // used only when the register-resident path does not cover (nx, shift).
 // thomas_dev: Thomas multipliers for the box spline (nx entries).
+// passes = 2 applies the same sweep twice in one launch (register-resident
+// path only; hipErrorInvalidValue otherwise), bitwise equal to two launches.
 // True when the register-resident sweep covers (nx, displacement); otherwise
 // launch_advect needs the state-sized `work` array.
 bool advect_in_registers(int nx, bool periodic, double max_cells);
 template <typename T>
 hipError_t launch_advect(const T* in, T* out, T* work, int nx, int nk, int dim, bool periodic,
                          double cells_per_p, double max_cells, const double* p_dev,
-                         const double* thomas_dev, hipStream_t st);
+                         const double* thomas_dev, hipStream_t st, int passes = 1);
 
 // Theta application on all nx*nx planes.
 //   mode 0: out = Theta[u]

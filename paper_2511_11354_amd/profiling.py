@@ -47,6 +47,8 @@ def kernel_class(name: str):
     m = re.match(r"k_theta<(\w+), (\d+), (\w+), (\w+), (\d)>", n)
     if m:
         return ("theta_stage1" if m.group(5) == "0" else "theta_stage2"), os.path.join(CSRC, "theta.hip")
+    if re.match(r"k_advect_reg<\w+, \d+, \w+, 2>", n):
+        return "advect_x1x1", os.path.join(CSRC, "advect.hip")
     if n.startswith("k_advect"):
         return "advect", os.path.join(CSRC, "advect.hip")
     return None

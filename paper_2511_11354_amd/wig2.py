@@ -49,7 +49,8 @@ class TrainCfg(ctypes.Structure):
 
 SUR_PARAMS = 625  # W1[16][20], b1[16], W2[16][16], b2[16], w3[16], b3
 
-PROF_NAMES = ("advect_x1", "advect_x2", "theta_stage1", "theta_stage2", "meanfield", "theta_heun")
+PROF_NAMES = ("advect_x1", "advect_x2", "theta_stage1", "theta_stage2", "meanfield", "theta_heun",
+              "advect_x1x1")
 
 FN1 = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_double, ctypes.c_void_p)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -73,6 +74,7 @@ SIGNATURES = {
     "wig2_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32], ctypes.c_int),
     "wig2_band": ([_vp], ctypes.c_int),
     "wig2_set_theta_path": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "wig2_set_sweep_fusion": ([_vp, ctypes.c_int32], ctypes.c_int),
     "wig2_theta_path": ([_vp], ctypes.c_int),
     "wig2_batch_create": ([ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params), _vp,
                            ctypes.POINTER(_vp)], ctypes.c_int),
@@ -245,6 +247,11 @@ class Solver:
         self._check(self._L.wig2_profile_read(self._h, _ptr(ms), cnt, int(reset)),
                     "wig2_profile_read")
         return {n: (float(ms[i]), int(cnt[i])) for i, n in enumerate(PROF_NAMES)}
+
+    def set_sweep_fusion(self, enable=True):
+        """Strang: run consecutive x1 half-sweeps of a multi-step call as one
+        launch (default) or as two."""
+        self._check(self._L.wig2_set_sweep_fusion(self._h, int(bool(enable))), "wig2_set_sweep_fusion")
 
     THETA_PATHS = {"auto": 0, "general": 1, "stream": 2}
 
