@@ -39,11 +39,15 @@ def short_name(name: str) -> str:
 def kernel_class(name: str):
     """(class, source file) of a kernel of this library, or None."""
     n = short_name(name)
-    m = re.match(r"k_theta_stream<(\w+), (\d+), (\w+), (\d)>", n)
+    m = re.match(r"k_theta_stream<(\w+), (\d+), (\w+), (\d)(?:, \d+)?>", n)
     if m:
         form = int(m.group(4))
         cls = {0: "theta_apply", 1: "theta_stage1", 2: "theta_stage2", 3: "theta_heun"}[form]
         return cls, os.path.join(CSRC, "theta_stream.hip")
+    m = re.match(r"k_theta_panel(?:_bf16)?<(?:\w+, )?(\d+), (\d)>", n)
+    if m:
+        cls = {0: "theta_apply", 1: "theta_stage1", 2: "theta_stage2"}[int(m.group(2))]
+        return cls, os.path.join(CSRC, "theta_panel.hip")
     m = re.match(r"k_theta<(\w+), (\d+), (\w+), (\w+), (\d)>", n)
     if m:
         return ("theta_stage1" if m.group(5) == "0" else "theta_stage2"), os.path.join(CSRC, "theta.hip")
@@ -97,7 +101,8 @@ def _counter_values(d, counter):
     return acc
 
 
-def traffic(fetch_dir, write_dir, copy_bytes, workload, precision, json_path=None, out=None):
+def traffic(fetch_dir, write_dir, copy_bytes, workload, precision, json_path=None, out=None,
+            commands=None):
     fv = _counter_values(fetch_dir, "FETCH_SIZE")
     wv = _counter_values(write_dir, "WRITE_SIZE")
     copies = [k for k in fv if "copy" in k.lower()]
@@ -111,7 +116,8 @@ def traffic(fetch_dir, write_dir, copy_bytes, workload, precision, json_path=Non
     fetch = {k: sum(v) / len(v) for k, v in fv.items()}
     write = {k: sum(v) / len(v) for k, v in wv.items()}
     nf = {k: len(v) for k, v in fv.items()}
-    lines = [f"Calibration: the largest dispatch of `{short_name(ck)}` copies {copy_bytes} bytes and reads "
+    lines = [f"Commands (from the repository root): {' ; '.join(f'`{c}`' for c in commands)}", ""] if commands else []
+    lines += [f"Calibration: the largest dispatch of `{short_name(ck)}` copies {copy_bytes} bytes and reads "
              f"FETCH_SIZE {cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB -> scale factors {ffac:.3f} (fetch), "
              f"{wfac:.3f} (write).  Per-kernel rows are means over dispatches.", "",
              "| kernel | dispatches | FETCH KiB | WRITE KiB | scaled GB read | scaled GB written | GB total |",
@@ -160,12 +166,13 @@ def main(argv=None):
     b.add_argument("--precision", required=True)
     b.add_argument("--json")
     b.add_argument("--out")
+    b.add_argument("--command", action="append", help="counter run command (repeat per run)")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         sys.stdout.write(stats(args.dir, args.command, args.out))
     else:
         sys.stdout.write(traffic(args.fetch, args.write, args.copy_bytes, args.workload,
-                                 args.precision, args.json, args.out))
+                                 args.precision, args.json, args.out, args.command))
 
 
 if __name__ == "__main__":
