@@ -262,12 +262,13 @@ const char* wig2_batch_last_error(const wig2_batch* b);
  * For a block of B fine steps from f_t, the exact block gives f_full and the
  * same B steps without Theta[V12] (Sec. 3.1.2) give f_nov; the model learns
  * Delta = f_full - f_nov as a function of f_t.  Model: per grid point an MLP
- * (2 tanh layers of 16) on the 17 values of f_t along the anti-diagonal
- * through the point (n1 - m, n2 + m), |m| <= 8, plus sin and cos of
- * 2 pi (i1 - i2)/nx and the pair strength U = V12(0); 625 parameters,
- * trained in FP32 with Adam on the GPU, applied with BF16 weights and FP32
- * arithmetic.  Torus contexts with a pair potential, FP64 or FP32, no mean
- * field.
+ * (2 tanh layers of 16) plus a linear path, on 20 features of f_t along the
+ * anti-diagonal through the point, v_m = f_t(n1 - m, n2 + m), in the form
+ * of the pair term (whose kernel is V12_m sin(m a), a = 2 pi (i1 - i2)/nx):
+ * v_0, sin(m a)(v_m - v_-m) and cos(m a)(v_m + v_-m) for m = 1..8, sin a,
+ * cos a and the pair strength U = V12(0); 645 parameters, trained in FP32
+ * with Adam on the GPU, applied with BF16 weights and FP32 arithmetic.
+ * Torus contexts with a pair potential, FP64 or FP32, no mean field.
  * ------------------------------------------------------------------------ */
 typedef struct wig2_surrogate wig2_surrogate;
 typedef struct {
@@ -298,13 +299,13 @@ int wig2_surrogate_collect(wig2_surrogate* s, wig2_ctx* ctx, int32_t blocks, int
  * epoch and of the last evaluation, Adam steps taken, samples seen. */
 int wig2_surrogate_stats(const wig2_surrogate* s, double* train_loss, double* eval_loss,
                          int64_t* updates, int64_t* samples);
-/* Parameters (FP32 master copy, 625 values: W1[16][20], b1, W2[16][16], b2,
- * w3, b3) and scales[3] = {in_scale, out_scale, U}.  set resets Adam. */
+/* Parameters (FP32 master copy, 645 values: W1[16][20], b1, W2[16][16], b2,
+ * w3, b3, a[20]) and scales[3] = {in_scale, out_scale, U}.  set resets Adam. */
 int wig2_surrogate_get_params(const wig2_surrogate* s, float* params, float* scales);
 int wig2_surrogate_set_params(wig2_surrogate* s, const float* params, const float* scales);
 /* Gradient of the mean squared error over all points of caller-owned device
  * fields ft and delta (the context's element type and grid) with the FP32
- * weights; grad[625] and the loss are written to host memory.  At most 2^22
+ * weights; grad[645] and the loss are written to host memory.  At most 2^22
  * points. */
 int wig2_surrogate_grad(wig2_surrogate* s, wig2_ctx* ctx, const void* ft_dev, const void* delta_dev,
                         float* grad, double* loss);

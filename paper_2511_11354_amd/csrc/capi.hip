@@ -1065,7 +1065,7 @@ int wig2_surrogate_create(const wig2_train_cfg* cfg, wig2_surrogate** out)
         wig2_surrogate_destroy(s);
         return WIG2_ENOMEM;
     }
-    // Xavier-uniform weights, zero biases
+    // Xavier-uniform weights, zero biases and linear path
     std::vector<float> p(kSurP, 0.f);
     const int D = kSurD, H = kSurH;
     auto fill = [&](int off, int n, int fan_in, int fan_out) {

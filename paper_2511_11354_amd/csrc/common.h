@@ -101,10 +101,11 @@ hipError_t launch_theta_panel(const ThetaArgs& a, const T* x, const T* y, T* out
                               double tau, hipStream_t st);
 
 // Learned pair-increment surrogate (surrogate.hip): per-point MLP with
-// kSurR anti-diagonal neighbours on each side, kSurH hidden units per layer.
+// kSurR anti-diagonal neighbours on each side, kSurH hidden units per layer,
+// plus a linear path from the kSurD features to the output.
 constexpr int kSurR = 8, kSurH = 16;
 constexpr int kSurD = 2 * kSurR + 1 + 3;
-constexpr int kSurP = kSurH * kSurD + kSurH + kSurH * kSurH + kSurH + kSurH + 1;
+constexpr int kSurP = kSurH * kSurD + kSurH + kSurH * kSurH + kSurH + kSurH + 1 + kSurD;
 struct SurScales {
     float in_scale;       // multiplies f_t in the features
     float out_scale;      // Delta = out_scale * y

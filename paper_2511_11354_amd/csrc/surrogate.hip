@@ -1,11 +1,17 @@
 // Learned surrogate for the pair-interaction increment over a block of fine
 // steps (the Theta[V12] part of the two-body operator, Sec. 3.1.2): a small
 // per-point MLP
-//   y(x) = w3 . tanh(W2 tanh(W1 x + b1) + b2) + b3,
-//   x = [s_in f_t(n1 - m, n2 + m), m = -R..R;  sin(2 pi l/nx), cos(2 pi l/nx), U],
+//   y(x) = w3 . tanh(W2 tanh(W1 x + b1) + b2) + b3 + a . x,
 // reads the block-start state along the anti-diagonal through the point (the
 // direction the pair term couples, l = i1 - i2) and predicts the increment
-// Delta / s_out.  Training: minibatch MSE with Adam; per workgroup the
+// Delta / s_out.  Its inputs follow the form of the pair term, whose kernel
+// is V12_m sin(2 pi m l / nx) on the antisymmetric differences
+// d_m = f(n1 - m, n2 + m) - f(n1 + m, n2 - m) (its square brings in
+// cos(2 pi m l / nx) on the symmetric sums e_m = f(n1 - m, n2 + m) +
+// f(n1 + m, n2 - m)):
+//   x = [s_in f_t(n1, n2);  s_in sin(2 pi m l/nx) d_m, m = 1..R;
+//        s_in cos(2 pi m l/nx) e_m, m = 1..R;  sin(2 pi l/nx), cos(2 pi l/nx), U]
+// with f_t = 0 off the p-box.  Training: minibatch MSE with Adam; per workgroup the
 // forward and backward passes of 256 sample points run in registers, the
 // per-sample activations go to LDS and the weight gradients are their sums
 // over the 256 samples (one partial per workgroup, reduced in the update
@@ -19,7 +25,8 @@ namespace {
 
 constexpr int R = kSurR, H = kSurH, D = kSurD, P = kSurP;
 constexpr int OW1 = 0, OB1 = H * D, OW2 = OB1 + H, OB2 = OW2 + H * H, OW3 = OB2 + H, OB3 = OW3 + H;
-static_assert(OB3 + 1 == P, "parameter layout");
+constexpr int OA = OB3 + 1;  // linear path a[D]
+static_assert(OA + D == P, "parameter layout");
 constexpr int TB = 256;  // samples per workgroup
 
 struct PointIdx {
@@ -46,10 +53,21 @@ template <typename T>
 __device__ inline void features(const T* ft, const PointIdx& q, int nk, const SurScales& sc, float x[D])
 {
     const T* F = ft + q.pl * (long)nk * nk;
-#pragma unroll
-    for (int m = -R; m <= R; ++m) {
+    auto at = [&](int m) {  // s_in f_t(n1 - m, n2 + m), zero off the p-box
         const int a = q.n1 - m, b = q.n2 + m;
-        x[m + R] = (a >= 0 && a < nk && b >= 0 && b < nk) ? sc.in_scale * (float)F[(long)a * nk + b] : 0.f;
+        return (a >= 0 && a < nk && b >= 0 && b < nk) ? sc.in_scale * (float)F[(long)a * nk + b] : 0.f;
+    };
+    x[0] = at(0);
+    // sin / cos of m * 2 pi l / nx by the angle-addition recurrence
+    float sm = q.cs, cm = q.cc;
+#pragma unroll
+    for (int m = 1; m <= R; ++m) {
+        const float lo = at(m), hi = at(-m);
+        x[m] = sm * (lo - hi);
+        x[R + m] = cm * (lo + hi);
+        const float sn = sm * q.cc + cm * q.cs;
+        cm = cm * q.cc - sm * q.cs;
+        sm = sn;
     }
     x[2 * R + 1] = q.cs;
     x[2 * R + 2] = q.cc;
@@ -75,6 +93,8 @@ __device__ inline float forward(const float* W, const float x[D], float h1[H], f
     float y = W[OB3];
 #pragma unroll
     for (int h = 0; h < H; ++h) y += W[OW3 + h] * h2[h];
+#pragma unroll
+    for (int d = 0; d < D; ++d) y += W[OA + d] * x[d];
     return y;
 }
 
@@ -168,8 +188,11 @@ __global__ __launch_bounds__(TB) void k_sur_batch(const T* ft, const T* delta, i
             } else if (j < OB3) {
                 const int h = j - OW3;
                 for (int s = 0; s < TB; ++s) g += DY[s] * H2[s][h];
-            } else {
+            } else if (j == OB3) {
                 for (int s = 0; s < TB; ++s) g += DY[s];
+            } else {
+                const int d = j - OA;
+                for (int s = 0; s < TB; ++s) g += DY[s] * X[s][d];
             }
             partial[(long)blockIdx.x * P + j] = g;
         }

@@ -47,7 +47,7 @@ class TrainCfg(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
-SUR_PARAMS = 625  # W1[16][20], b1[16], W2[16][16], b2[16], w3[16], b3
+SUR_PARAMS = 645  # W1[16][20], b1[16], W2[16][16], b2[16], w3[16], b3, a[20]
 
 PROF_NAMES = ("advect_x1", "advect_x2", "theta_stage1", "theta_stage2", "meanfield", "theta_heun",
               "advect_x1x1")

@@ -34,11 +34,17 @@ def test_features_direct_loop():
     rng = np.random.default_rng(4)
     for _ in range(50):
         i1, i2, n1, n2 = (int(v) for v in rng.integers(0, [nx, nx, nk, nk]))
-        for m in range(-S.R, S.R + 1):
-            a, b = n1 - m, n2 + m
-            want = 0.7 * ft[i1, i2, a, b] if (0 <= a < nk and 0 <= b < nk) else 0.0
-            assert Xr[i1, i2, n1, n2, m + S.R] == want
         ang = 2 * np.pi * ((i1 - i2) % nx) / nx
+
+        def v(m):
+            a, b = n1 - m, n2 + m
+            return 0.7 * ft[i1, i2, a, b] if (0 <= a < nk and 0 <= b < nk) else 0.0
+
+        assert Xr[i1, i2, n1, n2, 0] == v(0)
+        for m in range(1, S.R + 1):
+            assert np.isclose(Xr[i1, i2, n1, n2, m], np.sin(m * ang) * (v(m) - v(-m)), rtol=1e-15, atol=1e-15)
+            assert np.isclose(Xr[i1, i2, n1, n2, S.R + m], np.cos(m * ang) * (v(m) + v(-m)),
+                              rtol=1e-15, atol=1e-15)
         assert np.isclose(Xr[i1, i2, n1, n2, 2 * S.R + 1], np.sin(ang))
         assert np.isclose(Xr[i1, i2, n1, n2, 2 * S.R + 2], np.cos(ang))
         assert Xr[i1, i2, n1, n2, 2 * S.R + 3] == 1.3
