@@ -109,7 +109,9 @@ def cpu_baseline(w, f0, budget_s=20.0):
                         oracle.advect(g, 2, 0.5 * w.dt, f0, l0, n, out=out))
     # a pilot run sizes the sample so that it takes about budget_s in all:
     # half on Theta planes, half on sweep lines (both directions)
-    p0 = min(nplanes_all, 4)
+    # (the pilot takes at least two planes per oracle thread: fewer planes
+    # than threads would time a partly idle pool and undersize the sample)
+    p0 = min(nplanes_all, max(4, 2 * oracle.num_threads()))
     per_plane = timed(th, 0, p0) / p0
     l0 = min(nlines_all, w.nk * w.nk)
     per_line = timed(sw, 0, l0) / l0
