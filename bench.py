@@ -226,8 +226,10 @@ def bench_accuracy(a):
     128^4 workload (mixture seed 0): every form advances the same initial
     state by the same steps; at checkpoints the one-particle density n1 and
     the pair density n12 (FP64 reductions) are compared with FP64's, as
-    max|n - n_fp64| / max|n_fp64|, and the mass and energy drift are
-    recorded.  Rates are timed between checkpoints (observables excluded)."""
+    max|n - n_fp64| / max|n_fp64|, the state itself as eps_inf =
+    max|f - f_fp64| / max|f_fp64| and eps_2 = rms(f - f_fp64) / max|f_fp64|,
+    and the mass and energy drift are recorded.  Rates are timed between
+    checkpoints (observables and state copies excluded)."""
     import numpy as np
     import torch
 
@@ -239,7 +241,19 @@ def bench_accuracy(a):
     marks = sorted({m for m in (1, 10, 100, nsteps) if m <= nsteps})
     f0 = None
     ref = {}
+    fref = {}
     forms = {}
+
+    def state_errors(f, r):
+        # chunked over x1 slabs: eps_inf and eps_2 against the FP64 state
+        mx = num = 0.0
+        dmax = 0.0
+        for i in range(f.shape[0]):
+            d = f[i] - r[i]
+            dmax = max(dmax, float(np.abs(d).max()))
+            num += float(np.sum(d * d))
+            mx = max(mx, float(np.abs(r[i]).max()))
+        return dmax / mx, math.sqrt(num / f.size) / mx
     for prec in ("fp64", "fp32", "bf16x2"):
         s = wig2.Solver(w.nx, w.nk, x_min=w.x_min, x_max=w.x_max, dt=w.dt, precision=prec)
         s.set_potentials(w.vext, w.v12)
@@ -261,7 +275,9 @@ def bench_accuracy(a):
                    "energy_drift": abs(ob["energy"] - ob0["energy"]) / abs(ob0["energy"])}
             if prec == "fp64":
                 ref[m] = (ob["n1"].copy(), ob["n12"].copy(), ob["mass"], ob["energy"])
+                fref[m] = s.get_state()
             else:
+                row["eps_inf"], row["eps_2"] = state_errors(s.get_state(), fref[m])
                 n1r, n12r, mr, er = ref[m]
                 row["err_n1"] = float(np.abs(ob["n1"] - n1r).max() / np.abs(n1r).max())
                 row["err_n12"] = float(np.abs(ob["n12"] - n12r).max() / np.abs(n12r).max())
