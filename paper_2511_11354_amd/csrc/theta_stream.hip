@@ -19,7 +19,8 @@
 //   form 3: out = x + (tau/2)(Theta[x] + Theta[x + tau Theta[x]]), the whole
 //           Heun step with the plane kept in LDS between the two passes
 //           (Theta acts within each x-pair plane), so f is read and the
-//           result written once.
+//           result written once; evaluated as h + Theta[(tau/2) g] with
+//           h = x + (tau/2) Theta[x], g = x + tau Theta[x].
 // Heun's step f + (tau/2)(Theta f + Theta g), g = f + tau Theta f, is form 1
 // followed by form 2 with x = g, y = f, because (tau/2) Theta f = (g - f)/2.
 // out may alias x or y: plane p of x is read (into registers) one iteration
@@ -74,11 +75,16 @@ constexpr int stream_waves_per_eu()
 // Theta work on one plane held in LDS (X, and tk for the pair term), after
 // the barrier that published it: both passes for the one-pass Heun form,
 // one pass and the epilogue otherwise.  Ends with a barrier, after which X
-// may be rewritten.  Every thread of the workgroup calls it.
-template <typename T, int NK, bool TWO, int FORM, int WS>
+// may be rewritten.  Every thread of the workgroup calls it.  The one-pass
+// Heun form calls before_pass2() once the first pass no longer reads the
+// plane's registers (the caller issues the next plane's loads there).
+struct NoHook {
+    __device__ void operator()() const {}
+};
+template <typename T, int NK, bool TWO, int FORM, int WS, typename Hook = NoHook>
 __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl, const double* __restrict__ sig1,
                                              const double* __restrict__ sig2, int band, double tau, T* X,
-                                             const T* tk, int lane, int w, int J0)
+                                             const T* tk, int lane, int w, int J0, Hook before_pass2 = Hook())
 {
     typedef typename Acc<T>::V V;
     typedef StreamLayout<T, NK> L;
@@ -112,10 +118,12 @@ __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl
     auto row = [&](int q) { return 16 * w + acc_row<T>(el >> 4, q); };
     auto lds_at = [&](int j, int q) { return X + row(q) * LD + col(j, q); };
 
-    // acc = Theta of the plane held in X, at the lane-owned points
-    auto theta_pass = [&](V (&acc)[NSH]) {
+    // acc (+)= Theta of the plane held in X, at the lane-owned points
+    auto theta_pass = [&](V (&acc)[NSH], bool accumulate) {
+        if (!accumulate) {
 #pragma unroll
-        for (int j = 0; j < NSH; ++j) acc[j] = V{0, 0, 0, 0};
+            for (int j = 0; j < NSH; ++j) acc[j] = V{0, 0, 0, 0};
+        }
         if constexpr (TWO) {
             // Output tile (row block w, skewed tile j) covers s in
             // [16(w+j), 16(w+j)+16); the 16 rows k of block KB hold non-zero
@@ -170,12 +178,14 @@ __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl
     };
 
     V sacc[NSH];
-    theta_pass(sacc);
+    theta_pass(sacc, false);
 
     if constexpr (FORM == 3) {
         // Whole Heun step in one pass over the plane: h = f + tau/2 Theta f
-        // stays in registers, g = f + tau Theta f replaces f in LDS, and
-        // the second pass gives f' = h + tau/2 Theta g.
+        // stays in registers, (tau/2) g with g = f + tau Theta f replaces f in
+        // LDS, and the second pass accumulates Theta[(tau/2) g] = (tau/2)
+        // Theta g (Theta is linear) onto h: its accumulators are h, so the
+        // pass-one results need no registers of their own during pass 2.
         V hv[NSH];
         el = opaque_lane();
 #pragma unroll
@@ -184,7 +194,7 @@ __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl
             for (int q = 0; q < 4; ++q) {
                 const T fx = *lds_at(j, q);
                 hv[j][q] = fx + T(0.5 * tau) * sacc[j][q];
-                sacc[j][q] = fx + T(tau) * sacc[j][q];
+                sacc[j][q] = T(0.5 * tau) * (fx + T(tau) * sacc[j][q]);
             }
         __syncthreads();  // every wave is done reading f
         el = opaque_lane();
@@ -196,15 +206,15 @@ __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl
                 if (tile_ok(j) && n2 >= 0 && n2 < NK) *lds_at(j, q) = sacc[j][q];
             }
         __syncthreads();
-        theta_pass(sacc);
+        before_pass2();
+        theta_pass(hv, true);
         el = opaque_lane();
 #pragma unroll
         for (int j = 0; j < NSH; ++j) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int n1 = row(q), n2 = col(j, q);
-                if (tile_ok(j) && n2 >= 0 && n2 < NK)
-                    out[pbase + (long)n1 * NK + n2] = hv[j][q] + T(0.5 * tau) * sacc[j][q];
+                if (tile_ok(j) && n2 >= 0 && n2 < NK) out[pbase + (long)n1 * NK + n2] = hv[j][q];
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -315,11 +325,22 @@ __global__ __launch_bounds__(NK / 16 * 64 * WS, (stream_waves_per_eu<T, NK, FORM
         asm volatile("" : "+v"(t));
         return t;
     };
-    auto fetch = [&](long p) {
+    // The one-pass Heun form prefetches the first NVP loads of the next
+    // plane during its second pass (at nk = 128: all of them for FP32, half
+    // for FP64, whose second pass has no room for the whole plane in
+    // registers; none at smaller planes, where the spare registers buy more
+    // resident waves instead) and issues the rest at the top of the next
+    // iteration.
+    constexpr int NVP = FORM != 3 ? NV : NK != 128 ? 0 : sizeof(T) == 8 ? NV / 2 : NV;
+    auto fetch_range = [&](long p, int v0, int v1) {
         const VT* src = reinterpret_cast<const VT*>(x + p * (long)NK * NK);
         const int ot = opaque_tid();
 #pragma unroll
-        for (int v = 0; v < NV; ++v) xr[v] = src[ot + v * NT];
+        for (int v = 0; v < NV; ++v)
+            if (v >= v0 && v < v1) xr[v] = src[ot + v * NT];
+    };
+    auto fetch = [&](long p) {
+        fetch_range(p, 0, FORM == 3 ? NVP : NV);
         if constexpr (TWO) {
             if (tid < 2 * NK) {
                 const int i1 = (int)(p / nx), i2 = (int)(p % nx);
@@ -329,14 +350,12 @@ __global__ __launch_bounds__(NK / 16 * 64 * WS, (stream_waves_per_eu<T, NK, FORM
             }
         }
     };
-    // The one-pass Heun form holds h = f + tau/2 Theta f in registers
-    // instead of the next plane: it loads each plane at the top of its
-    // iteration.
-    constexpr bool PREFETCH = FORM != 3;
-    if constexpr (PREFETCH) fetch(pl);
+    // The one-pass Heun form issues the next plane's loads before its
+    // second pass, once the first pass's registers are free.
+    fetch(pl);
 
     for (; pl < np; pl += stride) {
-        if constexpr (!PREFETCH) fetch(pl);
+        if constexpr (FORM == 3 && NVP < NV) fetch_range(pl, NVP, NV);
         const int ot = opaque_tid();
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -350,11 +369,16 @@ __global__ __launch_bounds__(NK / 16 * 64 * WS, (stream_waves_per_eu<T, NK, FORM
             }
         }
         __syncthreads();
-        if constexpr (PREFETCH) {
+        if constexpr (FORM == 3) {
+            const long next = pl + stride;
+            stream_plane<T, NK, TWO, FORM, WS>(y, out, nx, pl, sig1, sig2, band, tau, X, tk, lane, w, J0,
+                                               [&]() {
+                                                   if (next < np) fetch(next);
+                                               });
+        } else {
             if (pl + stride < np) fetch(pl + stride);
+            stream_plane<T, NK, TWO, FORM, WS>(y, out, nx, pl, sig1, sig2, band, tau, X, tk, lane, w, J0);
         }
-
-        stream_plane<T, NK, TWO, FORM, WS>(y, out, nx, pl, sig1, sig2, band, tau, X, tk, lane, w, J0);
     }
 }
 
