@@ -132,31 +132,35 @@ __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl
             // outside the plane).
             const T* pa = tk + 16 * w + li + NK - lk;
             const T* pb = X + lk * (LD - 1) + 16 * (w + J0) + li;
+            // Operands of k-step kb + 1 are read from LDS while the matrix
+            // cores work on k-step kb (two register sets, software
+            // pipelined).  All operand reads are issued regardless of the
+            // (scalar) tile tests; reads of inactive tiles stay inside the
+            // LDS allocation (columns -127 .. 255 of rows 0 .. NK-1) and are
+            // not used.
+            T a[2], bv[2][NSH];
+            auto load = [&](int kb, int buf) {
+                a[buf] = pa[-4 * kb];
+#pragma unroll
+                for (int j = 0; j < NSH; ++j) bv[buf][j] = pb[4 * kb * (LD - 1) + 16 * j];
+            };
+            load(0, 0);
 #pragma unroll
             for (int KB = 0; KB < NW; ++KB) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int kb = 4 * KB + i;
-                    const T a = pa[-4 * kb];
-                    // All operand reads are issued before the (scalar)
-                    // tile tests; reads of inactive tiles stay inside the
-                    // LDS allocation (columns -127 .. 255 of rows 0 .. NK-1)
-                    // and are not used.
-                    T bv[NSH];
-#pragma unroll
-                    for (int j = 0; j < NSH; ++j) bv[j] = pb[4 * kb * (LD - 1) + 16 * j];
+                    const int kb = 4 * KB + i, cur = kb & 1;
+                    if (kb + 1 < 4 * NW) load(kb + 1, cur ^ 1);
 #pragma unroll
                     for (int j = 0; j < NSH; ++j) {
                         const int d = w + J0 + j - KB;
                         if (!tile_ok(j) || d < 0 || d > NW) continue;  // wave-uniform
-                        acc[j] = mma(a, bv[j], acc[j]);
+                        acc[j] = mma(a[cur], bv[cur][j], acc[j]);
                     }
-                    // the one-pass Heun form also holds h: fewer reads in flight
-                    if constexpr (FORM == 3) __builtin_amdgcn_sched_barrier(0);
+                    // keep the scheduler from hoisting further operand
+                    // reads of the unrolled loop (register pressure)
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                // keep the scheduler from hoisting every operand read of
-                // the unrolled loop (register pressure)
-                __builtin_amdgcn_sched_barrier(0);
             }
         }
         // single-body differences (modes 1..band of x_i1 along n1, of x_i2
