@@ -37,6 +37,9 @@ CASES = {
                                     (0.0, 0.03)], 20.0),
                    I.smoothed_coulomb(1.0, 1.0), "auto"),
     "box-33": (33, 32, False, 4, I.harmonic(0.5), None, "auto"),
+    # nx = 24 has no register-resident sweep: the general sweep kernel, and
+    # the two x1 half-sweeps as two launches through a work buffer
+    "general-sweep-24": (24, 32, True, 1, I.cosine(0.5, 20.0), I.smoothed_coulomb(1.0, 1.0), "stream"),
 }
 
 
