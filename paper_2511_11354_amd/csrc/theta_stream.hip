@@ -186,10 +186,16 @@ __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl
 
     if constexpr (FORM == 3) {
         // Whole Heun step in one pass over the plane: h = f + tau/2 Theta f
-        // stays in registers, (tau/2) g with g = f + tau Theta f replaces f in
-        // LDS, and the second pass accumulates Theta[(tau/2) g] = (tau/2)
-        // Theta g (Theta is linear) onto h: its accumulators are h, so the
-        // pass-one results need no registers of their own during pass 2.
+        // stays in registers and g = f + tau Theta f replaces f in LDS.
+        // FP64: LDS holds (tau/2) g instead, and the second pass accumulates
+        // Theta[(tau/2) g] = (tau/2) Theta g (Theta is linear) directly onto
+        // h (its accumulators are h, so the pass-one results need no
+        // registers of their own during pass 2).  FP32 keeps g and h apart
+        // and forms h + (tau/2) Theta g at the end: accumulating onto h would
+        // round at the scale of h once per matrix-core instruction, which
+        // biases the mass measurably over many steps, and the scaled operand
+        // adds a rounding to every product.
+        constexpr bool ONTO_H = sizeof(T) == 8;
         V hv[NSH];
         el = opaque_lane();
 #pragma unroll
@@ -198,7 +204,7 @@ __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl
             for (int q = 0; q < 4; ++q) {
                 const T fx = *lds_at(j, q);
                 hv[j][q] = fx + T(0.5 * tau) * sacc[j][q];
-                sacc[j][q] = T(0.5 * tau) * (fx + T(tau) * sacc[j][q]);
+                sacc[j][q] = ONTO_H ? T(0.5 * tau) * (fx + T(tau) * sacc[j][q]) : fx + T(tau) * sacc[j][q];
             }
         __syncthreads();  // every wave is done reading f
         el = opaque_lane();
@@ -211,7 +217,13 @@ __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl
             }
         __syncthreads();
         before_pass2();
-        theta_pass(hv, true);
+        if constexpr (ONTO_H) {
+            theta_pass(hv, true);
+        } else {
+            theta_pass(sacc, false);
+#pragma unroll
+            for (int j = 0; j < NSH; ++j) hv[j] += T(0.5 * tau) * sacc[j];
+        }
         el = opaque_lane();
 #pragma unroll
         for (int j = 0; j < NSH; ++j) {
