@@ -406,7 +406,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU slab "
-              "decomposition is a design, not part of this build.", file=sys.stderr)
+              "decomposition is a design, not implemented here.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

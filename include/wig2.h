@@ -45,7 +45,7 @@ extern "C" {
 #define WIG2_ENOMEM (-2)   /* device or host allocation failed                 */
 #define WIG2_EDEVICE (-3)  /* HIP runtime error (message has the HIP string)   */
 #define WIG2_ESTATE (-4)   /* call out of order (step before state/potentials)  */
-#define WIG2_ENOTSUP (-5)  /* combination not supported by this build          */
+#define WIG2_ENOTSUP (-5)  /* combination not supported by this library        */
 #define WIG2_ENUMERIC (-6) /* NaN or Inf met in the observables                */
 
 enum { WIG2_STRANG = 0, WIG2_LAWSON_PC = 1 };
