@@ -329,7 +329,7 @@ __global__ __launch_bounds__(64) void k_advect_any(const T* __restrict__ in, T* 
 // Batched sweep: every wave takes 64-line items from a list spanning all
 // instances of an ensemble (grid-stride, items pre-sorted by cost).
 // ---------------------------------------------------------------------------
-template <typename T, int NX>
+template <typename T, int NX, int PASSES>
 __global__ __launch_bounds__(256) void k_advect_batch(const T* __restrict__ in_pool,
                                                       T* __restrict__ out_pool,
                                                       const BatchInst* __restrict__ insts,
@@ -343,8 +343,8 @@ __global__ __launch_bounds__(256) void k_advect_batch(const T* __restrict__ in_p
         const BatchInst I = insts[item.inst];
         const long line = item.line0 + lane;
         if (line >= (long)NX * I.nk * I.nk) continue;
-        advect_line_reg<T, NX, true>(in_pool + I.off, out_pool + I.off, I.nk, dim, line, I.cpp,
-                                     p_pool + I.p_off, nullptr);
+        advect_line_reg<T, NX, true, PASSES>(in_pool + I.off, out_pool + I.off, I.nk, dim, line, I.cpp,
+                                             p_pool + I.p_off, nullptr);
     }
 }
 
@@ -372,13 +372,18 @@ bool batch_nx_ok(int nx)
 template <typename T>
 hipError_t launch_advect_batch(const T* in_pool, T* out_pool, const BatchInst* insts,
                                const AdvItem* items, int nitems, int dim, const double* p_pool,
-                               int nx, int grid, hipStream_t st)
+                               int nx, int grid, hipStream_t st, int passes)
 {
     if (nitems == 0) return hipSuccess;
-#define WIG2_ADV_BATCH(N)                                                                        \
-    case N:                                                                                      \
-        hipLaunchKernelGGL((k_advect_batch<T, N>), dim3(grid), dim3(256), 0, st, in_pool, out_pool, \
-                           insts, items, nitems, dim, p_pool);                                   \
+    if (passes != 1 && passes != 2) return hipErrorInvalidValue;
+#define WIG2_ADV_BATCH(N)                                                                          \
+    case N:                                                                                        \
+        if (passes == 2)                                                                           \
+            hipLaunchKernelGGL((k_advect_batch<T, N, 2>), dim3(grid), dim3(256), 0, st, in_pool,    \
+                               out_pool, insts, items, nitems, dim, p_pool);                       \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_advect_batch<T, N, 1>), dim3(grid), dim3(256), 0, st, in_pool,    \
+                               out_pool, insts, items, nitems, dim, p_pool);                       \
         return hipGetLastError();
     switch (nx) {
         WIG2_ADV_BATCH(16)
@@ -393,10 +398,10 @@ hipError_t launch_advect_batch(const T* in_pool, T* out_pool, const BatchInst* i
 }
 template hipError_t launch_advect_batch<double>(const double*, double*, const BatchInst*,
                                                 const AdvItem*, int, int, const double*, int, int,
-                                                hipStream_t);
+                                                hipStream_t, int);
 template hipError_t launch_advect_batch<float>(const float*, float*, const BatchInst*,
                                                const AdvItem*, int, int, const double*, int, int,
-                                               hipStream_t);
+                                               hipStream_t, int);
 
 bool advect_in_registers(int nx, bool periodic, double max_cells)
 {

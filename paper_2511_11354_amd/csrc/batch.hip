@@ -1,17 +1,19 @@
 // Batched ensembles of uneven periodic instances (C ABI wig2_batch_*).
 //
 // All instances live in three state pools (f, stage buffer, sweep buffer)
-// and two FP64 symbol pools.  One Strang step has six phases, each covering
-// every instance: two half-step sweeps, the two Theta stages, two half-step
-// sweeps.  Instances are grouped into size classes (nx, nk), heavy classes
-// split into several chains of similar work; per chain and phase there is
-// one persistent launch of a kernel specialised to that size (registers and
-// LDS exactly as for a single grid), walking a work list of
-// (instance, 64 lines) or (instance, planes) items.  Instances never
-// interact, so each chain's six launches are independent of the others: the
-// step's HIP graph forks one branch per chain (side streams during capture)
-// and joins them at the end of the step, letting the device run the chains
-// side by side.  The graph is captured once and replayed per step.  Tile
+// and two FP64 symbol pools.  One Strang step covers every instance with
+// two half-step sweeps, the Heun substep (two Theta stages, or the one-pass
+// Heun kernel) and two half-step sweeps; within one call the last x1
+// half-sweep of a step and the first of the next share one launch.
+// Instances are grouped into size classes (nx, nk), heavy classes split into
+// several chains of similar work; per chain and phase there is one
+// persistent launch of a kernel specialised to that size (registers and LDS
+// exactly as for a single grid), walking a work list of (instance, 64 lines)
+// or (instance, planes) items.  Instances never interact, so each chain's
+// launches are independent of the others: the HIP graphs fork one branch
+// per chain (side streams during capture) and join them at the end, letting
+// the device run the chains side by side.  The head, middle and tail
+// segments of a call are captured once as three graphs and replayed.  Tile
 // choices (planes per Theta workgroup per nk, grid sizes per class) come
 // from an autotuner that times the candidates on the ensemble itself and
 // keeps the winners in a small JSON cache keyed by architecture, precision
@@ -79,8 +81,8 @@ struct wig2_batch {
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> join;
     bool items_valid = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[3] = {};      // step segments: head, mid, tail
+    hipGraphExec_t exec[3] = {};
     bool graph_valid = false;
     std::string err;
 };
@@ -103,10 +105,12 @@ int bfail(wig2_batch* b, int code, const std::string& m)
 
 void drop_graph(wig2_batch* b)
 {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
+    for (int k = 0; k < 3; ++k) {
+        if (b->exec[k]) hipGraphExecDestroy(b->exec[k]);
+        if (b->graph[k]) hipGraphDestroy(b->graph[k]);
+        b->exec[k] = nullptr;
+        b->graph[k] = nullptr;
+    }
     b->graph_valid = false;
 }
 
@@ -207,10 +211,10 @@ int upload_insts(wig2_batch* b)
 
 template <typename T>
 hipError_t class_advect(wig2_batch* b, const wig2_batch::Cls& c, int dim, const void* in, void* out,
-                        int grid, hipStream_t st)
+                        int grid, hipStream_t st, int passes = 1)
 {
     return launch_advect_batch<T>((const T*)in, (T*)out, b->insts_d, b->adv_d + c.adv_begin, c.adv_count,
-                                  dim, b->p_pool, c.nx, grid, st);
+                                  dim, b->p_pool, c.nx, grid, st, passes);
 }
 
 template <typename T>
@@ -232,31 +236,44 @@ hipError_t class_heun(wig2_batch* b, const wig2_batch::Cls& c, void* f, int grid
     return e != hipSuccess ? e : class_theta<T>(b, c, 1, f, b->k1, f, grid, st);
 }
 
-// One Strang step of one size class (five or six launches on one stream):
-// half-step sweeps x1 then x2, Heun, half-step sweeps x2 then x1 (the sweep
-// order of a single context's step).
+// Strang steps of one size class, in the sweep order of a single context's
+// multi-step call: a step enters with the x1 then x2 half-sweeps and leaves
+// with x2 then x1, and between two steps of one call the two x1 half-sweeps
+// run as one two-pass launch.  A call of n steps is
+//   head (x1 f->tmp, x2 tmp->f, Heun f, x2 f->tmp)
+//   n - 1 times mid (x1 x1 tmp->k1, x2 k1->f, Heun f, x2 f->tmp)
+//   tail (x1 tmp->f),
+// so every segment starts and ends in the same pools (k1, the general
+// Heun's stage buffer, is free between Heun stages).
+enum Seg { SEG_HEAD = 0, SEG_MID = 1, SEG_TAIL = 2 };
+
 template <typename T>
-hipError_t class_step(wig2_batch* b, const wig2_batch::Cls& c, hipStream_t st)
+hipError_t class_seg(wig2_batch* b, const wig2_batch::Cls& c, int seg, hipStream_t st)
 {
     hipError_t e;
-    if ((e = class_advect<T>(b, c, 1, b->f, b->tmp, c.adv_grid, st)) != hipSuccess) return e;
-    if ((e = class_advect<T>(b, c, 2, b->tmp, b->f, c.adv_grid, st)) != hipSuccess) return e;
+    if (seg == SEG_TAIL) return class_advect<T>(b, c, 1, b->tmp, b->f, c.adv_grid, st);
+    if (seg == SEG_HEAD) {
+        if ((e = class_advect<T>(b, c, 1, b->f, b->tmp, c.adv_grid, st)) != hipSuccess) return e;
+        if ((e = class_advect<T>(b, c, 2, b->tmp, b->f, c.adv_grid, st)) != hipSuccess) return e;
+    } else {
+        if ((e = class_advect<T>(b, c, 1, b->tmp, b->k1, c.adv_grid, st, 2)) != hipSuccess) return e;
+        if ((e = class_advect<T>(b, c, 2, b->k1, b->f, c.adv_grid, st)) != hipSuccess) return e;
+    }
     if ((e = class_heun<T>(b, c, b->f, c.th_grid, st)) != hipSuccess) return e;
-    if ((e = class_advect<T>(b, c, 2, b->f, b->tmp, c.adv_grid, st)) != hipSuccess) return e;
-    return class_advect<T>(b, c, 1, b->tmp, b->f, c.adv_grid, st);
+    return class_advect<T>(b, c, 2, b->f, b->tmp, c.adv_grid, st);
 }
 
-// The whole step: one chain per class, forked from and joined back to the
-// batch stream (parallel branches under capture).
+// One segment for every class: one chain per class, forked from and joined
+// back to the batch stream (parallel branches under capture).
 template <typename T>
-hipError_t enqueue_step(wig2_batch* b)
+hipError_t enqueue_seg(wig2_batch* b, int seg)
 {
-    if (b->cls.size() == 1) return class_step<T>(b, b->cls[0], b->st);
+    if (b->cls.size() == 1) return class_seg<T>(b, b->cls[0], seg, b->st);
     hipError_t e = hipEventRecord(b->fork, b->st);
     if (e != hipSuccess) return e;
     for (size_t c = 0; c < b->cls.size(); ++c) {
         if ((e = hipStreamWaitEvent(b->side[c], b->fork, 0)) != hipSuccess) return e;
-        if ((e = class_step<T>(b, b->cls[c], b->side[c])) != hipSuccess) return e;
+        if ((e = class_seg<T>(b, b->cls[c], seg, b->side[c])) != hipSuccess) return e;
         if ((e = hipEventRecord(b->join[c], b->side[c])) != hipSuccess) return e;
     }
     for (size_t c = 0; c < b->cls.size(); ++c)
@@ -264,24 +281,36 @@ hipError_t enqueue_step(wig2_batch* b)
     return hipSuccess;
 }
 
+// One whole step (head then tail).
+template <typename T>
+hipError_t enqueue_step(wig2_batch* b)
+{
+    hipError_t e = enqueue_seg<T>(b, SEG_HEAD);
+    return e != hipSuccess ? e : enqueue_seg<T>(b, SEG_TAIL);
+}
+
+// Runs one step directly (kernel attributes are set by uncaptured launches
+// first; the joint x1 launch needs none), then captures the three segments.
 int capture(wig2_batch* b)
 {
     if (!b->items_valid && build_items(b)) return WIG2_EDEVICE;
     drop_graph(b);
-    // kernel attributes are set by a direct (uncaptured) launch first
     hipError_t e = b->elem == 8 ? enqueue_step<double>(b) : enqueue_step<float>(b);
     if (e != hipSuccess) return bfail(b, WIG2_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
     BCHK(b, hipStreamSynchronize(b->st));
-    BCHK(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeGlobal));
-    e = b->elem == 8 ? enqueue_step<double>(b) : enqueue_step<float>(b);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(b->st, &g);
-    if (e != hipSuccess || e2 != hipSuccess) {
-        if (g) hipGraphDestroy(g);
-        return bfail(b, WIG2_EDEVICE, "graph capture failed");
+    for (int seg = 0; seg < 3; ++seg) {
+        BCHK(b, hipStreamBeginCapture(b->st, hipStreamCaptureModeGlobal));
+        e = b->elem == 8 ? enqueue_seg<double>(b, seg) : enqueue_seg<float>(b, seg);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->st, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            drop_graph(b);
+            return bfail(b, WIG2_EDEVICE, "graph capture failed");
+        }
+        b->graph[seg] = g;
+        BCHK(b, hipGraphInstantiate(&b->exec[seg], g, nullptr, nullptr, 0));
     }
-    b->graph = g;
-    BCHK(b, hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
     b->graph_valid = true;
     return WIG2_OK;
 }
@@ -542,13 +571,16 @@ int wig2_batch_step(wig2_batch* b, int64_t nsteps)
     if (!b || nsteps < 0) return WIG2_EINVAL;
     for (auto& h : b->inst)
         if (!h.has_pot || !h.has_state) return bfail(b, WIG2_ESTATE, "every instance needs potentials and a state");
+    if (nsteps == 0) return WIG2_OK;
     if (!b->graph_valid) {
         int rc = capture(b);
         if (rc) return rc;
         --nsteps;  // the capture pass ran one step directly
-        if (nsteps < 0) return WIG2_OK;
+        if (nsteps == 0) return WIG2_OK;
     }
-    for (int64_t s = 0; s < nsteps; ++s) BCHK(b, hipGraphLaunch(b->exec, b->st));
+    BCHK(b, hipGraphLaunch(b->exec[SEG_HEAD], b->st));
+    for (int64_t s = 1; s < nsteps; ++s) BCHK(b, hipGraphLaunch(b->exec[SEG_MID], b->st));
+    BCHK(b, hipGraphLaunch(b->exec[SEG_TAIL], b->st));
     return WIG2_OK;
 }
 

@@ -210,7 +210,7 @@ hipError_t launch_theta_stream_batch(T* pool, const BatchInst* insts, const ThIt
 template <typename T>
 hipError_t launch_advect_batch(const T* in_pool, T* out_pool, const BatchInst* insts,
                                const AdvItem* items, int nitems, int dim, const double* p_pool,
-                               int nx, int grid, hipStream_t st);
+                               int nx, int grid, hipStream_t st, int passes = 1);
 template <typename T>
 hipError_t launch_theta_batch(const T* u_pool, const T* v_pool, T* out_pool,
                               const BatchInst* insts, const ThItem* items, int nitems, int mode,
