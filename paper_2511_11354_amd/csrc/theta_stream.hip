@@ -69,7 +69,7 @@ struct StreamLayout {
 template <typename T, int NK, int FORM, int WS>
 constexpr int stream_waves_per_eu()
 {
-    return (sizeof(T) == 4 && NK == 128 && FORM != 3 && WS == 1) ? 4 : 1;
+    return (sizeof(T) == 4 && NK == 128 && FORM != 3 && WS == 1) ? 4 : (sizeof(T) == 4 && NK <= 64) ? 2 : 1;
 }
 
 // Theta work on one plane held in LDS (X, and tk for the pair term), after
@@ -453,7 +453,8 @@ hipError_t go_stream_nk(const ThetaArgs& a, const T* x, const T* y, T* out, int 
 // in place (the same per-plane arithmetic as a single context).
 // ---------------------------------------------------------------------------
 template <typename T, int NK>
-__global__ __launch_bounds__(NK / 16 * 64) void k_theta_stream_batch(T* pool, const BatchInst* __restrict__ insts,
+__global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, 3, 1>())) void k_theta_stream_batch(
+    T* pool, const BatchInst* __restrict__ insts,
                                                                    const ThItem* __restrict__ items, int nitems,
                                                                    const double* __restrict__ sig_pool,
                                                                    const double* __restrict__ kap_pool)
@@ -561,13 +562,14 @@ bool batch_stream_nk_ok(int nk, int elem_bytes)
 }
 
 // Plane sizes where the streaming kernel beats the general one (measured on
-// MI355X, Strang steps of 64^2 x nk^2 and 128^4 with a one-mode V_ext): the
-// one-pass Heun form needs more registers per wave than small planes can
-// afford at the occupancy their LDS footprint would allow.
+// MI355X, Strang steps of nk^4 with a one-mode V_ext; FP32 at nk = 48 and 64
+// and FP64 at 48 the general kernel is faster): the one-pass Heun form needs
+// more registers per wave than those planes can afford at the occupancy
+// their LDS footprint would allow.
 bool theta_stream_preferred(int nk, int elem_bytes)
 {
     if (elem_bytes == 8) return nk == 32 || nk == 64 || nk == 96 || nk == 128;
-    return nk == 128;
+    return nk == 32 || nk == 128;
 }
 
 template <typename T>

@@ -147,9 +147,9 @@ def test_stream_path_selection():
     s3 = wig2.Solver(8, 64, dt=0.01, precision="bf16x2")
     s3.set_potentials(I.cosine(0.5, 20.0), None)
     assert s3.theta_path() == "general"
-    # automatic choice by plane size: FP64 64 and FP32 128 stream, FP32 64 general
+    # automatic choice by plane size: FP64 64 and FP32 32, 128 stream, FP32 64 general
     for prec, nk, want in (("fp64", 64, "stream"), ("fp32", 128, "stream"), ("fp32", 64, "general"),
-                           ("fp64", 48, "general")):
+                           ("fp32", 32, "stream"), ("fp64", 48, "general")):
         s4 = wig2.Solver(4, nk, dt=0.01, precision=prec)
         s4.set_potentials(I.cosine(0.5, 20.0), I.smoothed_coulomb(1.0, 1.0))
         assert s4.theta_path() == want, (prec, nk)
