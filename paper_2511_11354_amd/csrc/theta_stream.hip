@@ -49,16 +49,21 @@ struct Vec16<float> {
     static constexpr int N = 4;
 };
 
-// LDS plane: rows -PADR .. NK+PADR-1 at pitch LD = NK + kPadCols; the
-// PADR rows above and below the plane and the kPadCols columns after each
-// row stay zero, so every read of the single-body differences (rows n1 +- m,
-// columns n2 +- m, m <= kStreamBand) and of the skewed pair operand (columns
-// -18 .. NK+17) lands on plane data or on a zero, with no bounds test.
+// LDS plane: rows -PADR .. NK+PADR-1 at pitch LD = NK + PADC; the PADR
+// rows above and below the plane and the PADC columns after each row stay
+// zero, so every read of the single-body differences (rows n1 +- m, columns
+// n2 +- m, m <= kStreamBand) and of the skewed pair operand of a visited
+// tile (columns -15 .. NK+15: a column c < 0 of row k is column LD + c of
+// row k - 1) lands on plane data or on a zero, with no bounds test.  PADC
+// >= 16 is chosen with LD - 1 = 16 (mod 32): the four k-rows of an operand
+// read (row step LD - 1 in the skewed layout) then fall on disjoint groups
+// of LDS banks, for 4- and 8-byte elements.
 template <typename T, int NK>
 struct StreamLayout {
     static constexpr int PADR = kStreamBand;
-    static constexpr int LD = NK + kPadCols;
-    static constexpr int PADC = LD - NK;
+    static constexpr int R32 = ((17 - NK) % 32 + 32) % 32;  // LD - 1 = 16 (mod 32)
+    static constexpr int PADC = R32 >= 16 ? R32 : R32 + 32;
+    static constexpr int LD = NK + PADC;
     static constexpr int X_ELEMS = (NK + 2 * PADR) * LD;
     static constexpr int TAB = 2 * NK;
     static constexpr size_t bytes = sizeof(T) * (size_t)(X_ELEMS + TAB);
@@ -478,7 +483,7 @@ __global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, 3, 1>()))
         Xbase[e] = T(0);
         X[NK * LD + e] = T(0);
     }
-    for (int e = tid; e < NK * kPadCols; e += NT) X[(e / kPadCols) * LD + NK + e % kPadCols] = T(0);
+    for (int e = tid; e < NK * L::PADC; e += NT) X[(e / L::PADC) * LD + NK + e % L::PADC] = T(0);
 
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const ThItem item = items[it];
