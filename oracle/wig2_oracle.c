@@ -14,6 +14,10 @@
  * own closed form in Sec. 5.1.1, so the first-principles sign is used here.
  * The two-body pseudo-difference formula (Sec. 3.1.2, eq. two_body_FSM) is
  * consistent as printed.
+ *
+ * Parity unpinned: or_hl (the Hedin-Lundqvist functional) only.  Every other
+ * routine is pinned by tests/test_oracle_pins.py to closed forms, exact
+ * identities, convergence rates or brute force.
  */
 #include "wig2_oracle.h"
 
@@ -192,7 +196,9 @@ void or_densities(const or_grid* g, const double* f, double* n1, double* n2)
 /* Hedin-Lundqvist exchange-correlation potential (Sec. 2.2) in atomic units
  * (hbar = e = m = 4 pi eps0 = 1, a_B = 1).  Then g_D = 0.985 n0^{1/3} and
  *   V_xc(n) = 0.985 n^{1/3} + 0.985*0.034 ln(1 + 18.37 n^{1/3}),
- * signs as printed; the density is clamped at zero. */
+ * signs as printed; the density is clamped at zero.
+ * Parity unpinned: the paper prints no value of this functional to check it
+ * against (its constants are 3-D physical-unit formulas). */
 static double or_hl(double n)
 {
     double c = cbrt(n > 0.0 ? n : 0.0);

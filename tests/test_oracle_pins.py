@@ -345,3 +345,160 @@ def test_sem_harmonic_is_classical_force(orc):
     ex = om**2 * x[:, None] * (-4 * (p[None, :] - 0.3)) * np.exp(-2 * (p[None, :] - 0.3) ** 2)
     mid = np.abs(x) < 4.0
     assert np.abs(th[mid] - ex[mid]).max() < 1e-6 * np.abs(ex[mid]).max() + 1e-9
+
+
+# --------------------------------------------------------------------------
+# mean field, dense operator orientation, potential energy, box step
+# --------------------------------------------------------------------------
+
+
+def test_meanfield_chain_closed_form(orc):
+    """The density-driven part of V_eff (Sec. 2.3) on the Sec. 5.1.1 test.
+    f = pi^-2 e^{-(x1+r1)^2/2 - 2p1^2} e^{-(x2+r2)^2/2 - 2p2^2} has the
+    densities n_j(x) = (2pi)^{-1/2} e^{-(x+r_j)^2/2}, which is exactly the
+    potential of that test.  A Hartree kernel V12(x_i - x_j) = delta_ij / dx
+    with lambda = 1 turns the Hartree sum into V_eff = n_j, so the chain
+    densities -> V_eff -> x-grid symbol -> Theta must give the closed form of
+    Sec. 5.1.1 on both particles at once.  Different r1, r2 catch swapped
+    densities; the 1/dx kernel catches a dropped dx; the closed form fixes the
+    symbol's sign and index order (x_i - x_j)."""
+    nx, nk = 128, 64           # nx = 2 nk: the x-grid resolves every p-shift
+    g = orc.grid(nx, nk, True, 1, -10.0, 10.0)
+    x = orc.xnodes(g)
+    p, _ = orc.pnodes(g)
+    dx = orc.dx(g)
+    r1, r2 = 1.0, -0.5
+    A = np.exp(-(x[:, None] + r1) ** 2 / 2 - 2 * p[None, :] ** 2)
+    B = np.exp(-(x[:, None] + r2) ** 2 / 2 - 2 * p[None, :] ** 2)
+    f = np.empty((nx, nx, nk, nk))
+    for i1 in range(nx):
+        f[i1] = np.pi**-2 * A[i1][None, :, None] * B[:, None, :]
+    n1, n2 = orc.densities(g, f)
+    ex_n1 = np.exp(-(x + r1) ** 2 / 2) / math.sqrt(2 * math.pi)
+    ex_n2 = np.exp(-(x + r2) ** 2 / 2) / math.sqrt(2 * math.pi)
+    assert np.abs(n1 - ex_n1).max() <= 1e-15 and np.abs(n2 - ex_n2).max() <= 1e-15
+    hartree = np.ascontiguousarray(np.eye(nx) / dx)
+    v1 = orc.veff_hxc(g, 1.0, False, 1.0, 1.0, hartree, n1)
+    v2 = orc.veff_hxc(g, 1.0, False, 1.0, 1.0, hartree, n2)
+    assert np.abs(v1 - ex_n1).max() <= 1e-15 and np.abs(v2 - ex_n2).max() <= 1e-15
+    # lambda scales the Hartree term linearly
+    assert np.abs(orc.veff_hxc(g, 0.5, False, 1.0, 1.0, hartree, n1) - 0.5 * ex_n1).max() <= 1e-15
+    s1, s2 = orc.sigma_hxc(g, v1), orc.sigma_hxc(g, v2)
+    planes = sorted({0, nx * nx - 1, 60 * nx + 66, 58 * nx + 70, 64 * nx + 64, 50 * nx + 75,
+                     70 * nx + 55, 62 * nx + 69, 3 * nx + 120})
+    th = np.zeros_like(f)
+    for pl in planes:
+        orc.theta_periodic(g, s1, s2, np.zeros(nk), f, False, pl, 1, out=th)
+    X1, X2, P1, P2 = _mesh(x, p)
+    worst, scale = 0.0, 0.0
+    for pl in planes:
+        i1, i2 = divmod(pl, nx)
+        e1 = (np.exp(-3 * (x[i1] + r1) ** 2 / 4 - p[:, None] ** 2) * np.sin((x[i1] + r1) * p[:, None])
+              * np.exp(-(x[i2] + r2) ** 2 / 2 - 2 * p[None, :] ** 2))
+        e2 = (np.exp(-(x[i1] + r1) ** 2 / 2 - 2 * p[:, None] ** 2)
+              * np.exp(-3 * (x[i2] + r2) ** 2 / 4 - p[None, :] ** 2) * np.sin((x[i2] + r2) * p[None, :]))
+        ex = np.pi**-2.5 * (e1 + e2)
+        worst = max(worst, np.abs(th[i1, i2] - ex).max())
+        scale = max(scale, np.abs(ex).max())
+    assert scale > 5e-3
+    assert worst <= 1e-15
+
+
+def test_dense_theta_orientation_harmonic(orc):
+    """or_theta_dense with the SEM matrix of V = omega^2 x^2 / 2 on both
+    particles (Sec. 3.2.1): for a quadratic potential the Wigner operator is
+    exactly omega^2 (x1 d/dp1 + x2 d/dp2) f (Sec. 2.3 with V''' = 0).  The
+    state differs between the particles in every variable, so applying K2 to
+    the wrong index, transposing it, or taking x1 for x2 fails."""
+    om = 0.5
+    g = orc.grid(121, 8 * 16, False, 8, -12.0, 12.0, k_max=6.0)
+    xf = orc.xnodes(g)
+    p, _ = orc.pnodes(g)
+    Kf = orc.sem_kernel(g, [I.harmonic(om)(v) for v in xf])
+    # eight x-nodes in the middle of the box, where the SEM operator of the
+    # quadratic potential is accurate; the sub-grid reuses their matrices
+    idx = np.array([44, 49, 55, 58, 61, 66, 70, 77])
+    x = xf[idx]
+    K = np.ascontiguousarray(Kf[idx])
+    gs = orc.grid(len(idx), g.nk, False, 8, -12.0, 12.0, k_max=6.0)
+    ga = np.exp(-(x[:, None] - 0.7) ** 2 / 3)
+    gb = np.exp(-(x[:, None] + 0.4) ** 2 / 5)
+    ua, ub = 0.3, -0.45
+    pa = np.exp(-2.0 * (p - ua) ** 2)
+    pb = np.exp(-1.5 * (p - ub) ** 2)
+    f = np.ascontiguousarray(ga[:, None, :, None] * gb[None, :, :, None]
+                             * pa[None, None, :, None] * pb[None, None, None, :])
+    th = orc.theta_dense(gs, K, K, f)
+    dpa = -4.0 * (p - ua) * pa
+    dpb = -3.0 * (p - ub) * pb
+    ex = om**2 * (x[:, None, None, None] * ga[:, None, :, None] * gb[None, :, :, None]
+                  * dpa[None, None, :, None] * pb[None, None, None, :]
+                  + x[None, :, None, None] * ga[:, None, :, None] * gb[None, :, :, None]
+                  * pa[None, None, :, None] * dpb[None, None, None, :])
+    assert np.abs(ex).max() > 0.1
+    assert np.abs(th - ex).max() <= 1e-6 * np.abs(ex).max()
+
+
+def test_potential_energy_closed_form(orc):
+    """Potential part of the energy (Sec. 2.2) for a product of Gaussian
+    packets with x-marginals of mean a_j and unit variance:
+    <V0 cos(k x_j)> = V0 cos(k a_j) e^{-k^2/2} and
+    <U cos(k (x1 - x2))> = U cos(k (a1 - a2)) e^{-k^2}, k = 2 pi / L.  A
+    dropped V12 term, a V12 of x1 + x2, or V_ext on one particle only fails."""
+    L = 20.0
+    g = orc.grid(64, 64, True, 1, -L / 2, L / 2)
+    x = orc.xnodes(g)
+    p, _ = orc.pnodes(g)
+    a1, q1, a2, q2 = -2.0, 0.5, 1.5, -0.25
+    Wa = I.cross_wigner(x[:, None], p[None, :], a1, q1, a1, q1).real
+    Wb = I.cross_wigner(x[:, None], p[None, :], a2, q2, a2, q2).real
+    f = np.ascontiguousarray(np.einsum("ac,bd->abcd", Wa, Wb))
+    v0, u = 0.7, 1.3
+    k = 2 * np.pi / L
+    vext = v0 * np.cos(k * x)
+    r = orc.pair_separations(g)
+    v12 = np.ascontiguousarray(u * np.cos(k * r))
+    ob = orc.observables(g, f, vext, v12)
+    ekin = (q1**2 / 2 + 1 / 8) + (q2**2 / 2 + 1 / 8)
+    epot = (v0 * (np.cos(k * a1) + np.cos(k * a2)) * np.exp(-k * k / 2)
+            + u * np.cos(k * (a1 - a2)) * np.exp(-k * k))
+    assert abs(ob["energy"] - (ekin + epot)) <= 1e-10
+    # each part alone
+    ob_ext = orc.observables(g, f, vext, np.zeros_like(v12))
+    assert abs(ob_ext["energy"] - ekin - v0 * (np.cos(k * a1) + np.cos(k * a2)) * np.exp(-k * k / 2)) <= 1e-10
+
+
+@pytest.mark.parametrize("scheme", ["strang", "lawson"])
+def test_box_step_harmonic_rotation(orc, scheme):
+    """Whole steps on the box (natural-boundary spline, SEM single-body
+    operator; Sec. 3.2, 4.1) under V = omega^2 x^2 / 2.  The Wigner flow of a
+    quadratic potential is the classical one, a rigid rotation of phase space:
+    f(x, p, t) = f0(x cos wt - (p/mw) sin wt, p cos wt + m w x sin wt) for each
+    particle.  Two different packets rotate by 1.2 rad; the step error falls
+    with tau (time error O(tau^2) above a spatial floor from the spline's h^4
+    and the SEM x-sum) and is small next to the rotation itself, while the
+    rotation the other way is far off."""
+    om, T, sg = 0.5, 2.4, 0.6
+    g = orc.grid(57, 32, False, 4, -7.0, 7.0, k_max=3.0)
+    x = orc.xnodes(g)
+    p, _ = orc.pnodes(g)
+    tb = orc.tables(g, I.harmonic(om), None)
+
+    def rotated(t):
+        c, s = np.cos(om * t), np.sin(om * t)
+        X0 = x[:, None] * c - p[None, :] / om * s
+        P0 = p[None, :] * c + om * x[:, None] * s
+        A = np.exp(-((X0 - 1.2) ** 2 + P0**2) / (2 * sg * sg))
+        B = np.exp(-((X0 + 0.8) ** 2 + (P0 - 0.6) ** 2) / (2 * sg * sg))
+        return np.ascontiguousarray(np.einsum("ac,bd->abcd", A, B))
+
+    f0, fe, fback = rotated(0.0), rotated(T), rotated(-T)
+    errs = []
+    for nst in (12, 24):
+        fo = orc.step(g, f0, tb, nst, T / nst, scheme=scheme, two_body=False)
+        errs.append(orc.errors(fo, fe)[0])
+    moved = orc.errors(f0, fe)[0]
+    wrong_way = orc.errors(fo, fback)[0]
+    assert moved > 0.5 and wrong_way > 0.5
+    assert errs[1] < 8e-3
+    assert errs[0] / errs[1] > 2.4
