@@ -103,8 +103,11 @@ int bfail(wig2_batch* b, int code, const std::string& m)
                          std::string(#call) + ": " + hipGetErrorString(e_));            \
     } while (0)
 
+// Graph execs may still be running on b->st (and, through the captured
+// fork/join events, on the side streams that b->st waits for).
 void drop_graph(wig2_batch* b)
 {
+    if (b->st) hipStreamSynchronize(b->st);
     for (int k = 0; k < 3; ++k) {
         if (b->exec[k]) hipGraphExecDestroy(b->exec[k]);
         if (b->graph[k]) hipGraphDestroy(b->graph[k]);
@@ -139,6 +142,8 @@ int build_items(wig2_batch* b)
     }
     std::vector<ThItem> thv;
     std::vector<AdvItem> av;
+    // the work lists below are freed and rewritten: wait for launches that read them
+    BCHK(b, hipStreamSynchronize(b->st));
     b->cls.clear();
     for (auto& kv : chains) {
         const int nx = kv.first.first, nk = kv.first.second;
@@ -169,8 +174,9 @@ int build_items(wig2_batch* b)
     b->adv_d = nullptr;
     BCHK(b, hipMalloc(&b->th_d, thv.size() * sizeof(ThItem)));
     BCHK(b, hipMalloc(&b->adv_d, av.size() * sizeof(AdvItem)));
-    BCHK(b, hipMemcpy(b->th_d, thv.data(), thv.size() * sizeof(ThItem), hipMemcpyHostToDevice));
-    BCHK(b, hipMemcpy(b->adv_d, av.data(), av.size() * sizeof(AdvItem), hipMemcpyHostToDevice));
+    BCHK(b, hipMemcpyAsync(b->th_d, thv.data(), thv.size() * sizeof(ThItem), hipMemcpyHostToDevice, b->st));
+    BCHK(b, hipMemcpyAsync(b->adv_d, av.data(), av.size() * sizeof(AdvItem), hipMemcpyHostToDevice, b->st));
+    BCHK(b, hipStreamSynchronize(b->st));
     b->nth = (int)thv.size();
     b->nadv = (int)av.size();
     while (b->side.size() < b->cls.size()) {
@@ -204,7 +210,9 @@ int upload_insts(wig2_batch* b)
         d.cpp = 0.5 * h.prm.dt / (h.g.mass * h.g.dx());
         d.tau = h.prm.dt;
     }
-    BCHK(b, hipMemcpy(b->insts_d, v.data(), v.size() * sizeof(BatchInst), hipMemcpyHostToDevice));
+    // ordered after every launch already queued on b->st that reads the table
+    BCHK(b, hipMemcpyAsync(b->insts_d, v.data(), v.size() * sizeof(BatchInst), hipMemcpyHostToDevice, b->st));
+    BCHK(b, hipStreamSynchronize(b->st));
     drop_graph(b);
     return WIG2_OK;
 }
@@ -530,8 +538,9 @@ int wig2_batch_set_potentials(wig2_batch* b, int32_t i, wig2_fn1 v_ext, wig2_fn1
             r -= L * std::floor((r + 0.5 * L) / L);
             h.v12pair[(size_t)a * nx + c] = V(v12, r);
         }
-    BCHK(b, hipMemcpy(b->sig_pool + h.tab_off, s.data(), s.size() * 8, hipMemcpyHostToDevice));
-    BCHK(b, hipMemcpy(b->kap_pool + h.tab_off, kap.data(), kap.size() * 8, hipMemcpyHostToDevice));
+    BCHK(b, hipMemcpyAsync(b->sig_pool + h.tab_off, s.data(), s.size() * 8, hipMemcpyHostToDevice, b->st));
+    BCHK(b, hipMemcpyAsync(b->kap_pool + h.tab_off, kap.data(), kap.size() * 8, hipMemcpyHostToDevice, b->st));
+    BCHK(b, hipStreamSynchronize(b->st));
     h.has_pot = true;
     return upload_insts(b);
 }
@@ -540,12 +549,15 @@ int wig2_batch_set_state(wig2_batch* b, int32_t i, const double* fh)
 {
     if (!b || !fh || i < 0 || i >= b->n) return WIG2_EINVAL;
     HostInst& h = b->inst[i];
+    // on b->st, after the steps still in flight that read or write the pool
     if (b->elem == 8) {
-        BCHK(b, hipMemcpy((double*)b->f + h.off, fh, h.npts() * 8, hipMemcpyHostToDevice));
+        BCHK(b, hipMemcpyAsync((double*)b->f + h.off, fh, h.npts() * 8, hipMemcpyHostToDevice, b->st));
+        BCHK(b, hipStreamSynchronize(b->st));
     } else {
         std::vector<float> t(h.npts());
         for (long k = 0; k < h.npts(); ++k) t[k] = (float)fh[k];
-        BCHK(b, hipMemcpy((float*)b->f + h.off, t.data(), h.npts() * 4, hipMemcpyHostToDevice));
+        BCHK(b, hipMemcpyAsync((float*)b->f + h.off, t.data(), h.npts() * 4, hipMemcpyHostToDevice, b->st));
+        BCHK(b, hipStreamSynchronize(b->st));
     }
     h.has_state = true;
     return WIG2_OK;
@@ -557,10 +569,12 @@ int wig2_batch_get_state(wig2_batch* b, int32_t i, double* fh)
     HostInst& h = b->inst[i];
     BCHK(b, hipStreamSynchronize(b->st));
     if (b->elem == 8) {
-        BCHK(b, hipMemcpy(fh, (double*)b->f + h.off, h.npts() * 8, hipMemcpyDeviceToHost));
+        BCHK(b, hipMemcpyAsync(fh, (double*)b->f + h.off, h.npts() * 8, hipMemcpyDeviceToHost, b->st));
+        BCHK(b, hipStreamSynchronize(b->st));
     } else {
         std::vector<float> t(h.npts());
-        BCHK(b, hipMemcpy(t.data(), (float*)b->f + h.off, h.npts() * 4, hipMemcpyDeviceToHost));
+        BCHK(b, hipMemcpyAsync(t.data(), (float*)b->f + h.off, h.npts() * 4, hipMemcpyDeviceToHost, b->st));
+        BCHK(b, hipStreamSynchronize(b->st));
         for (long k = 0; k < h.npts(); ++k) fh[k] = t[k];
     }
     return WIG2_OK;

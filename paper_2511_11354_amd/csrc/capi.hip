@@ -776,7 +776,8 @@ int wig2_set_potentials(wig2_ctx* c, wig2_fn1 v_ext, wig2_fn1 v12, void* user)
         if (upload(c, c->ksem_d, K)) return WIG2_EDEVICE;
         if (c->ksem_f) {
             const std::vector<float> Kf(K.begin(), K.end());
-            HIPCHK(c, hipMemcpy(c->ksem_f, Kf.data(), Kf.size() * sizeof(float), hipMemcpyHostToDevice));
+            HIPCHK(c, hipMemcpyAsync(c->ksem_f, Kf.data(), Kf.size() * sizeof(float), hipMemcpyHostToDevice, c->st));
+            HIPCHK(c, hipStreamSynchronize(c->st));
         }
         c->two_body = false;
         c->band = nk;

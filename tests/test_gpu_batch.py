@@ -65,6 +65,26 @@ def test_batch_equals_single_instances(precision):
         s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_reset_after_steps(precision):
+    """Setting one instance's state (and potentials) right after steps were
+    queued is ordered after them: the instance then evolves bitwise as in a
+    fresh batch, and its neighbours are untouched by the reset."""
+    b, pots, states = _build(precision)
+    b.step(1)
+    b.step(3)            # graph replays still in flight when the setters run
+    b.set_state(2, states[2])
+    b.set_potentials(2, *pots[2])
+    b.step(2)
+    fresh, _, _ = _build(precision)
+    fresh.step(2)
+    a2, f2 = b.get_state(2), fresh.get_state(2)
+    assert np.array_equal(a2, f2), np.abs(a2 - f2).max()
+    ref0 = _build(precision)[0]
+    ref0.step(6)
+    assert np.array_equal(b.get_state(0), ref0.get_state(0))
+
+
 def test_batch_fp64_matches_oracle(orc):
     b, pots, states = _build("fp64")
     b.step(3)

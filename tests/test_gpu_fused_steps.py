@@ -40,6 +40,14 @@ CASES = {
     # nx = 24 has no register-resident sweep: the general sweep kernel, and
     # the two x1 half-sweeps as two launches through a work buffer
     "general-sweep-24": (24, 32, True, 1, I.cosine(0.5, 20.0), I.smoothed_coulomb(1.0, 1.0), "stream"),
+    # 1024 planes of nk = 128: several planes per persistent workgroup, so the
+    # cross-plane prefetch of the one-pass Heun kernel runs as at 128^4
+    "stream-32x128": (32, 128, True, 1, I.cosine(0.5, 20.0), I.smoothed_coulomb(2.0, 1.0), "stream"),
+    # nx = 128: the register-resident sweep of 128-point lines, and the joint
+    # two-pass x1 launch of the 128^4 workload
+    "stream-128x32": (128, 32, True, 1, I.cosine(0.5, 20.0), I.smoothed_coulomb(1.0, 1.0), "stream"),
+    # nx = 129 box: the natural-boundary register sweep of the box workload
+    "box-129": (129, 32, False, 4, I.harmonic(0.5), None, "auto"),
 }
 
 
@@ -63,6 +71,7 @@ def make(case, precision, fused=True):
     return s, f0
 
 
+@pytest.mark.timeout(300)
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", sorted(CASES))
 @pytest.mark.parametrize("n", [3, 4])
@@ -88,6 +97,7 @@ def test_multi_step_bitwise(case, precision, n):
     assert np.array_equal(many, unfused)
 
 
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_multi_step_matches_oracle(orc, case):
     nx, nk, per, cells, vext, v12, _ = CASES[case]
@@ -101,3 +111,22 @@ def test_multi_step_matches_oracle(orc, case):
     e = eps_inf(s.get_state(), ref)
     print(f"{case}: 6 steps in one call vs oracle eps_inf {e:.3e}", flush=True)
     assert e <= 1e-12
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("case", ["stream-32x128", "stream-128x32", "box-129"])
+def test_multi_step_fp32_matches_oracle(orc, case):
+    """The FP32 form of the same launch configurations, 3 steps in one call,
+    against the FP64 oracle at the FP32 bound (state rounding ~6e-8 per step
+    plus FP32 operator sums)."""
+    nx, nk, per, cells, vext, v12, _ = CASES[case]
+    s, f0 = make(case, "fp32")
+    s.step(3)
+    if per:
+        g = orc.grid(nx, nk, True, 1, -10.0, 10.0)
+    else:
+        g = orc.grid(nx, nk, False, cells, -15.0, 15.0, 10.0 * np.pi / 3.0)
+    ref = orc.step(g, f0, orc.tables(g, vext, v12), 3, 0.005)
+    e = eps_inf(s.get_state(), ref)
+    print(f"{case} fp32: 3 steps in one call vs oracle eps_inf {e:.3e}", flush=True)
+    assert e <= 2e-6

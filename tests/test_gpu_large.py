@@ -124,3 +124,20 @@ def test_step_mid_size_full_parity(orc):
     e = np.abs(s.get_state() - ref).max() / np.abs(ref).max()
     print(f"64^4 one step eps_inf {e:.3e}")
     assert e <= 1e-12
+
+
+@pytest.mark.timeout(900)
+def test_two_steps_full_grid_vs_oracle(orc, big):
+    """The benchmark's 128^4 FP64 workload, two Strang steps in one call (the
+    one-pass Heun kernel with its cross-plane prefetch over all 16384 planes,
+    and the joint two-pass x1 launch between the steps), compared point by
+    point over the whole grid with two oracle steps."""
+    w, s, g, f0, tb = big
+    s.set_state(f0)
+    s.step(2)
+    got = s.get_state()
+    print("128^4: two GPU steps done, running two oracle steps", flush=True)
+    ref = orc.step(g, f0, tb, 2, w.dt)
+    e = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    print(f"128^4 two steps, full grid: eps_inf {e:.3e}", flush=True)
+    assert e <= 1e-12

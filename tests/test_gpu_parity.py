@@ -193,6 +193,28 @@ def test_step_meanfield_fp64(orc, lam, xc, scheme):
     assert e <= 1e-12
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("scheme", ["strang", "lawson"])
+def test_step_meanfield_nk128_fp64(orc, scheme):
+    """Hartree mean field (lambda = 1) at nk = 128, the plane size of the
+    128^4 workload: every lambda != 0 step takes the general kernel with the
+    dense single-body band (band = nk), rebuilt from the density each Theta
+    sub-step."""
+    nx, nk = 16, 128
+    vext, v12 = I.cosine(0.5, 20.0), I.smoothed_coulomb(1.0, 1.0)
+    s, g = make(orc, nx, nk, dt=0.005, scheme=scheme, vext=vext, v12=v12, meanfield_lambda=1.0)
+    assert s.band() == nk - 1 and s.theta_path() == "general"
+    x, p, _ = s.nodes()
+    f0 = I.mixture(x, p, seed=5, period=20.0)
+    tb = orc.tables(g, vext, v12)
+    s.set_state(f0)
+    s.step(3)
+    ref = orc.step(g, f0, tb, 3, 0.005, scheme=scheme, lam=1.0)
+    e = eps_inf(s.get_state(), ref)
+    print(f"meanfield nk=128 lam=1 {scheme}: 3 steps eps_inf {e:.3e}", flush=True)
+    assert e <= 1e-12
+
+
 def test_step_box_sem_fp64(orc):
     """Non-periodic box with the SEM single-body operator at a reduced shape
     (33 x-nodes, 4 cells x 8 nodes), harmonic V_ext, no V12."""
