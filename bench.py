@@ -81,7 +81,18 @@ def load_traffic(kernel_file, kernel_class, workload, precision):
         return None
 
 
-def cpu_baseline(w, f0, budget_s=20.0):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, f0, budget_s=20.0, gpu_theta=None, gpu_advect=None):
     """The CPU oracle timed on a bounded sample of the same workload: Theta on
     a set of x-pair planes and spline sweeps on a set of lines, scaled to one
     whole step (2 Theta + 4 sweeps) per grid point."""
@@ -117,16 +128,38 @@ def cpu_baseline(w, f0, budget_s=20.0):
     per_line = timed(sw, 0, l0) / l0
     npl = max(1, min(nplanes_all - p0, int(0.5 * budget_s / per_plane)))
     nli = max(1, min(nlines_all - l0, int(0.5 * budget_s / per_line)))
-    s_theta, s_sweep = timed(th, p0, npl), timed(sw, l0, nli)
+    s_theta = timed(th, p0, npl)
+    err = None
+    if gpu_theta is not None:
+        # the GPU path's Theta of the same state against the oracle's on the
+        # sampled planes (written by the timed call)
+        sl = slice(p0 * w.nk * w.nk, (p0 + npl) * w.nk * w.nk)
+        r, o = out.reshape(-1)[sl], gpu_theta.reshape(-1)[sl]
+        err = {"eps_inf_theta": float(np.abs(o - r).max() / np.abs(r).max()),
+               "theta_planes": [p0, p0 + npl - 1]}
+    s_sweep = timed(sw, l0, nli)
     t_theta = s_theta / npl * nplanes_all
     t_sweep = s_sweep / (2 * nli) * nlines_all
     t_step = 2 * t_theta + 4 * t_sweep
+    if gpu_advect is not None:
+        # the GPU path's x1 half-step sweep against the oracle's on a run of
+        # lines through the packets (untimed)
+        nli_e = min(nlines_all, 8 * w.nk * w.nk)
+        le = (w.nx // 2) * w.nk * w.nk - nli_e // 2
+        oracle.advect(g, 1, 0.5 * w.dt, f0, le, nli_e, out=out)
+        nk2 = w.nk * w.nk
+        lines = np.arange(le, le + nli_e)
+        o_, rem = lines // nk2, lines % nk2
+        idx = (o_ * nk2 + rem)[:, None] + np.arange(w.nx)[None, :] * w.nx * nk2
+        r, o = out.reshape(-1)[idx], gpu_advect.reshape(-1)[idx]
+        err = dict(err or {}, eps_inf_advect_x1=float(np.abs(o - r).max() / np.abs(r).max()),
+                   advect_lines=[int(le), int(le + nli_e - 1)])
     return {"value": w.points / t_step, "unit": "point-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": (f"FP64 oracle on {npl} of {nplanes_all} x-pair planes (Theta) and "
                        f"{nli} of {nlines_all} lines per sweep direction, scaled to one step "
                        f"of 2 Theta + 4 sweeps"),
-            "sample_s": s_theta + s_sweep, "s_per_step_extrapolated": t_step}
+            "sample_s": s_theta + s_sweep, "s_per_step_extrapolated": t_step, "error_vs_oracle": err}
 
 
 def bench_surrogate(a):
@@ -398,8 +431,12 @@ def main():
                          "split-BF16 against FP64 at 128^4 over --steps steps")
     ap.add_argument("--potential", default="harmonic", choices=["harmonic", "double_well"],
                     help="V_ext of the box workload")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "profiles", "tune_cache.json"),
-                    help="autotuner cache for the ensemble workload")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"),
+                    help="autotuner cache for the ensemble workload (runtime output, untracked)")
+    ap.add_argument("--forms", default="fp32,bf16x2,hartree",
+                    help="extra legs of the default 128^4 line, comma separated: fp32, bf16x2 "
+                         "(same workload and steps, errors against the FP64 run's final state) "
+                         "and hartree (FP64 with the mean field lambda = 1); empty for none")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain device copies of the state size (for counter scaling)")
@@ -418,6 +455,7 @@ def main():
     torch.cuda.set_device(0)
     if a.workload == "ensemble":
         a.precision = a.precision or "fp32"
+        os.makedirs(os.path.dirname(os.path.abspath(a.tune_cache)), exist_ok=True)
         return bench_ensemble(a)
     if a.workload == "surrogate":
         return bench_surrogate(a)
@@ -427,63 +465,153 @@ def main():
     a.precision = a.precision or ("fp32" if box else "fp64")
     if box:
         w = I.box_sem(129, 16, 16, a.potential)
-        s = wig2.Solver(w.nx, w.nk, periodic=False, sem_cells=w.cells, x_min=w.x_min,
-                        x_max=w.x_max, k_max=w.k_max, dt=w.dt, scheme=a.scheme,
-                        precision=a.precision)
     else:
         w = I.large_periodic(u=1.0) if a.workload == "large" else I.tiny_periodic()
-        s = wig2.Solver(w.nx, w.nk, x_min=w.x_min, x_max=w.x_max, dt=w.dt, scheme=a.scheme,
-                        precision=a.precision)
-    s.set_potentials(w.vext, w.v12)
-    x, p, _ = s.nodes()
+    probe = make_solver(w, box, a.scheme, "fp64")
+    x, p, _ = probe.nodes()
+    probe.close()
     if a.workload == "large":
         f0 = I.mixture(x, p, seed=0, period=w.x_max - w.x_min)
     elif box:
         f0 = I.symmetrised_pair(x, p, a=(-2.0, 2.0), q=(0.0, 0.0))
     else:
         f0 = I.symmetrised_pair(x, p)
+
+    forms = [f for f in a.forms.split(",") if f] if (a.workload == "large" and a.precision == "fp64") else []
+    main_leg = run_form(w, f0, box, a.scheme, a.precision, a.steps, a.warmup,
+                        keep_state=bool(forms), copy_calibration=a.copy_calibration,
+                        gpu_samples=not a.no_cpu and a.workload == "large" and a.precision == "fp64")
+    cpu = None
+    if not a.no_cpu and a.workload == "large" and a.precision == "fp64":
+        cpu = cpu_baseline(w, f0, gpu_theta=main_leg.pop("gpu_theta"), gpu_advect=main_leg.pop("gpu_advect"))
+    main_leg.pop("gpu_theta", None)
+    main_leg.pop("gpu_advect", None)
+    ref_state = main_leg.pop("state", None)
+    ref_obs = main_leg.pop("obs")
+    legs = {}
+    for form in forms:
+        prec, lam = ("fp64", 1.0) if form == "hartree" else (form, 0.0)
+        leg = run_form(w, f0, box, a.scheme, prec, a.steps, a.warmup, lam=lam, keep_state=lam == 0.0)
+        ob = leg.pop("obs")
+        st = leg.pop("state", None)
+        if st is not None:
+            e_inf, e_2 = state_errors(st, ref_state)
+            leg["error_vs_fp64"] = {
+                "eps_inf": e_inf, "eps_2": e_2,
+                "n1": rel_max(ob["n1"], ref_obs["n1"]), "n12": rel_max(ob["n12"], ref_obs["n12"]),
+                "mass": abs(ob["mass"] - ref_obs["mass"]) / abs(ref_obs["mass"]),
+                "after_steps": a.warmup + a.steps,
+                "definition": "max|x - x_fp64| / max|x_fp64| (eps_2: rms); the FP64 leg's final state"}
+        else:
+            leg["note"] = ("Hartree mean field lambda = 1 rebuilt from the density each Theta "
+                           "sub-step: dense single-body band, general Theta kernel")
+        del st
+        legs[form] = leg
+    out = {
+        "metric": METRIC, "value": main_leg["value"], "unit": "point-updates/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": main_leg["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[a.precision], "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "nk": w.nk, "points": w.points, "dt": w.dt,
+                   "scheme": a.scheme, "precision": a.precision, "V12_U": w.extra.get("U", 1.0),
+                   "single_body_band": main_leg["band"], "theta_kernel": main_leg["theta_kernel"],
+                   "seed": 0},
+        "error": ({"vs": "FP64 CPU oracle", **cpu["error_vs_oracle"]} if cpu and cpu.get("error_vs_oracle")
+                  else None),
+        "roofline": main_leg["roofline"], "cpu_baseline": cpu, "kernels": main_leg["kernels"],
+        "observables": {k: ref_obs[k] for k in ("mass", "energy", "entropy", "step")},
+        "forms": legs,
+    }
+    print(json.dumps(out))
+
+
+def make_solver(w, box, scheme, precision, lam=0.0):
+    from paper_2511_11354_amd import wig2
+
+    if box:
+        return wig2.Solver(w.nx, w.nk, periodic=False, sem_cells=w.cells, x_min=w.x_min,
+                           x_max=w.x_max, k_max=w.k_max, dt=w.dt, scheme=scheme, precision=precision)
+    return wig2.Solver(w.nx, w.nk, x_min=w.x_min, x_max=w.x_max, dt=w.dt, scheme=scheme,
+                       precision=precision, meanfield_lambda=lam)
+
+
+def rel_max(a, b):
+    import numpy as np
+
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def state_errors(f, r):
+    """eps_inf and eps_2 of f against r, one x1 slab at a time."""
+    import numpy as np
+
+    mx = num = dmax = 0.0
+    for i in range(f.shape[0]):
+        d = f[i] - r[i]
+        dmax = max(dmax, float(np.abs(d).max()))
+        num += float(np.sum(d * d))
+        mx = max(mx, float(np.abs(r[i]).max()))
+    return dmax / mx, math.sqrt(num / f.size) / mx
+
+
+def run_form(w, f0, box, scheme, precision, steps, warmup, lam=0.0, keep_state=False,
+             copy_calibration=False, gpu_samples=False):
+    """One form of the workload: warm-up, then `steps` timed steps with the
+    per-kernel-class HIP event timing on the context stream."""
+    import torch
+
+    s = make_solver(w, box, scheme, precision, lam)
+    s.set_potentials(w.vext, w.v12)
     s.set_state(f0)
     band = s.band()
-
-    s.step(a.warmup)
+    res = {}
+    if gpu_samples:
+        # the FP64 path's Theta and x1 sweep of the initial state, checked
+        # against the oracle on the CPU-baseline sample
+        fin = torch.from_numpy(f0).cuda()
+        out = torch.empty_like(fin)
+        s.theta(fin, out)
+        res["gpu_theta"] = out.cpu().numpy()
+        s.advect(1, 0.5 * w.dt, fin, out)
+        res["gpu_advect"] = out.cpu().numpy()
+        del fin, out
+    s.step(warmup)
     torch.cuda.synchronize()
     s.profile(True)
     s.profile_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.step(a.steps)
+    s.step(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = s.profile_read(reset=True)
     s.profile(False)
     ob = s.observables()
-    if a.copy_calibration:
+    if copy_calibration:
         # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE
         # counters calibrate the byte counts read for the method's kernels
-        src = torch.empty(w.points * (8 if a.precision == "fp64" else 4), dtype=torch.uint8,
-                          device="cuda")
+        src = torch.empty(w.points * (8 if precision == "fp64" else 4), dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-
     npts = w.points
-    value = npts * a.steps / dt
-    elem = 8 if a.precision == "fp64" else 4
+    elem = 8 if precision == "fp64" else 4
+    dense_band = w.nk - 1 if lam != 0.0 else band
     kernels = {}
     for name, (ms, cnt) in prof.items():
         if cnt == 0:
             continue
-        by, fl = kernel_model(name, npts, elem, w.nk, band, a.precision, dense=box)
+        by, fl = kernel_model(name, npts, elem, w.nk, dense_band, precision, dense=box)
         avg = ms / cnt / 1e3
         kernels[name] = {"avg_ms": ms / cnt, "launches": cnt, "GB/s": by / avg / 1e9,
                          "TFLOP/s": fl / avg / 1e12}
     dom = max(prof, key=lambda k: prof[k][0])
     ms, cnt = prof[dom]
-    by, fl = kernel_model(dom, npts, elem, w.nk, band, a.precision, dense=box)
+    by, fl = kernel_model(dom, npts, elem, w.nk, dense_band, precision, dense=box)
     avg = ms / cnt / 1e3
-    pk_fl = PEAK["fp64" if a.precision == "fp64" else ("fp32" if a.precision == "fp32" else "bf16")]
+    pk_fl = PEAK["fp64" if precision == "fp64" else ("fp32" if precision == "fp32" else "bf16")]
     t_hbm = by / (PEAK["hbm_gbs"] * 1e9)
     t_fl = fl / (pk_fl * 1e12)
     if dom.startswith("theta") and t_fl > t_hbm:
@@ -491,32 +619,25 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": by / avg / 1e9, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    theta_file = ("theta_panel.hip" if box and w.nk == 256 else
-                  "theta_stream.hip" if s.theta_path() == "stream" else "theta.hip")
+    path = s.theta_path()
+    theta_file = ("theta_panel.hip" if path == "panel" else
+                  "theta_stream.hip" if path == "stream" else "theta.hip")
     kfile = os.path.join("paper_2511_11354_amd", "csrc",
                          theta_file if dom.startswith("theta") else "advect.hip")
-    roof["traffic"] = load_traffic(kfile, dom, w.name, a.precision)
+    roof["traffic"] = load_traffic(kfile, dom, w.name, precision)
     roof["kernel"] = dom
     roof["algorithmic_bytes_per_launch"] = by
     roof["algorithmic_flops_per_launch"] = fl
     roof["avg_launch_ms"] = ms / cnt
-
-    cpu = None
-    if not a.no_cpu and a.workload == "large" and a.precision == "fp64":
-        cpu = cpu_baseline(w, f0)
-    out = {
-        "metric": METRIC, "value": value, "unit": "point-updates/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt / a.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": DTYPE[a.precision], "data": "synthetic",
-        "config": {"workload": w.name, "nx": w.nx, "nk": w.nk, "points": npts, "dt": w.dt,
-                   "scheme": a.scheme, "precision": a.precision, "V12_U": w.extra.get("U", 1.0),
-                   "single_body_band": band, "theta_kernel": s.theta_path(), "seed": 0},
-        "roofline": roof, "cpu_baseline": cpu, "kernels": kernels,
-        "observables": {"mass": ob["mass"], "energy": ob["energy"], "entropy": ob["entropy"],
-                        "step": ob["step"]},
-    }
-    print(json.dumps(out))
+    res.update({"value": npts * steps / dt, "ms_per_step": dt / steps * 1e3, "roofline": roof,
+                "kernels": kernels, "theta_kernel": path, "band": band, "obs": ob,
+                "precision": precision, "meanfield_lambda": lam})
+    if keep_state:
+        res["state"] = s.get_state()
+    s.close()
+    del s
+    torch.cuda.synchronize()
+    return res
 
 
 if __name__ == "__main__":

@@ -133,6 +133,21 @@ int wig2_state_buffer(wig2_ctx* ctx, void** f_dev, int32_t* elem_bytes);
 /* Mark the state buffer as initialised after the caller wrote it. */
 int wig2_state_written(wig2_ctx* ctx);
 
+/* Bind a caller-owned device buffer as the state (the problem of Sec. 2.4 is
+ * posed on the caller's f(x1, x2, p1, p2)): from then on wig2_step,
+ * wig2_observables, wig2_get_state / wig2_set_state and the surrogate read
+ * and write f_dev in place, in the layout above; the context's own state
+ * buffer is left unused.  f_dev: nx*nx*nk*nk elements on the context's
+ * device, 16-byte aligned, holding the initial state (the step count and
+ * time restart at 0).  dtype: WIG2_FP64 for an FP64 context, WIG2_FP32 for
+ * FP32 and BF16X2 contexts (else WIG2_EINVAL, as for host or other-device
+ * memory).  The buffer stays caller-owned: it must outlive its binding and
+ * must not be written by others while a call on the context may use it
+ * (calls are ordered on the context stream).  f_dev == NULL unbinds: the
+ * context returns to its own buffer, which then needs wig2_set_state.
+ * Synchronises the context stream first. */
+int wig2_bind_state(wig2_ctx* ctx, void* f_dev, int32_t dtype);
+
 /* Advance nsteps steps of the configured scheme (asynchronous).
  * Strang (Sec. 4.1 splitting of the advection from the Theta term): each
  * step is A(dt/2), Heun on Theta with V_eff frozen, A(dt/2), where the

@@ -21,7 +21,8 @@ struct wig2_ctx {
     bool own_stream = false;
     int elem = 8;
     long npts = 0;
-    void* f = nullptr;
+    void* f = nullptr;       // the state: f_own, or a caller-owned buffer (wig2_bind_state)
+    void* f_own = nullptr;   // state buffer allocated by the context
     void* k1 = nullptr;
     void* tmp = nullptr;
     void* work = nullptr;  // lazily allocated advection scratch
@@ -668,9 +669,10 @@ int wig2_create(const wig2_grid* grid, const wig2_params* prm, void* hip_stream,
         c->own_stream = true;
     }
     const size_t bytes = (size_t)c->npts * c->elem;
-    if (hipMalloc(&c->f, bytes) != hipSuccess || hipMalloc(&c->k1, bytes) != hipSuccess ||
+    if (hipMalloc(&c->f_own, bytes) != hipSuccess || hipMalloc(&c->k1, bytes) != hipSuccess ||
         hipMalloc(&c->tmp, bytes) != hipSuccess)
         return bail(WIG2_ENOMEM);
+    c->f = c->f_own;
     const int nx = G.nx, nk = G.nk;
     const size_t np = (size_t)nx * nx;
     if (dev_alloc(c, &c->p_d, nk) || dev_alloc(c, &c->w_d, nk) || dev_alloc(c, &c->thomas_d, nx) ||
@@ -712,7 +714,7 @@ void wig2_destroy(wig2_ctx* c)
 {
     if (!c) return;
     if (c->st) hipStreamSynchronize(c->st);
-    void* bufs[] = {c->f, c->k1, c->tmp, c->work, c->p_d, c->w_d, c->thomas_d, c->sig_ext_d, c->sig1_d,
+    void* bufs[] = {c->f_own, c->k1, c->tmp, c->work, c->p_d, c->w_d, c->thomas_d, c->sig_ext_d, c->sig1_d,
                     c->sig2_d, c->kap_d, c->ksem_d, c->ksem_f, c->v12pair_d, c->sintab_d,
                     c->mf_dens_d, c->mf_veff_d, c->s0_d, c->s0b_d, c->skin_d, c->s2_d, c->rows_d,
                     c->f1_d, c->ft, c->fs};
@@ -828,6 +830,37 @@ int wig2_state_buffer(wig2_ctx* c, void** fd, int32_t* eb)
     if (!c || !fd) return WIG2_EINVAL;
     *fd = c->f;
     if (eb) *eb = c->elem;
+    return WIG2_OK;
+}
+
+int wig2_bind_state(wig2_ctx* c, void* f_dev, int32_t dtype)
+{
+    if (!c) return WIG2_EINVAL;
+    // work already queued on the context stream may still use the old buffer
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (!f_dev) {
+        c->f = c->f_own;
+        c->has_state = false;
+        c->err.clear();
+        return WIG2_OK;
+    }
+    const int32_t want = c->elem == 8 ? WIG2_FP64 : WIG2_FP32;
+    if (dtype != want)
+        return fail(c, WIG2_EINVAL, c->elem == 8 ? "bind_state: this context steps an FP64 state (dtype WIG2_FP64)"
+                                                 : "bind_state: this context steps an FP32 state (dtype WIG2_FP32)");
+    if (reinterpret_cast<uintptr_t>(f_dev) % 16 != 0)
+        return fail(c, WIG2_EINVAL, "bind_state: the buffer must be 16-byte aligned");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, f_dev) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+        attr.device != c->device) {
+        (void)hipGetLastError();
+        return fail(c, WIG2_EINVAL, "bind_state: not device memory of this context's device");
+    }
+    c->f = f_dev;
+    c->has_state = true;
+    c->nstep = 0;
+    c->t = 0.0;
+    c->err.clear();
     return WIG2_OK;
 }
 

@@ -65,6 +65,7 @@ SIGNATURES = {
     "wig2_get_state": ([_vp, _dp], ctypes.c_int),
     "wig2_state_buffer": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "wig2_state_written": ([_vp], ctypes.c_int),
+    "wig2_bind_state": ([_vp, _vp, ctypes.c_int32], ctypes.c_int),
     "wig2_step": ([_vp, ctypes.c_int64], ctypes.c_int),
     "wig2_observables": ([_vp, ctypes.POINTER(Obs), _dp, _dp, _dp], ctypes.c_int),
     "wig2_theta": ([_vp, _vp, _vp], ctypes.c_int),
@@ -218,6 +219,18 @@ class Solver:
     def state_written(self):
         self._check(self._L.wig2_state_written(self._h), "wig2_state_written")
 
+    def bind_state(self, f_dev):
+        """Step a caller-owned device tensor in place (None unbinds).  The
+        tensor must outlive the binding."""
+        if f_dev is None:
+            self._check(self._L.wig2_bind_state(self._h, None, 0), "wig2_bind_state")
+            self._bound = None
+            return
+        assert tuple(f_dev.shape) == self.shape
+        dtype = FP64 if self.precision == "fp64" else FP32
+        self._check(self._L.wig2_bind_state(self._h, _dev(f_dev), dtype), "wig2_bind_state")
+        self._bound = f_dev
+
     def step(self, n=1):
         self._check(self._L.wig2_step(self._h, int(n)), "wig2_step")
 
@@ -356,6 +369,18 @@ class Batch:
         f = np.empty(self.shapes[i], dtype=np.float64)
         self._check(self._L.wig2_batch_get_state(self._h, i, _ptr(f)), "wig2_batch_get_state")
         return f
+
+    def bind_state(self, f_dev):
+        """Step a caller-owned device tensor in place (None unbinds).  The
+        tensor must outlive the binding."""
+        if f_dev is None:
+            self._check(self._L.wig2_bind_state(self._h, None, 0), "wig2_bind_state")
+            self._bound = None
+            return
+        assert tuple(f_dev.shape) == self.shape
+        dtype = FP64 if self.precision == "fp64" else FP32
+        self._check(self._L.wig2_bind_state(self._h, _dev(f_dev), dtype), "wig2_bind_state")
+        self._bound = f_dev
 
     def step(self, n=1):
         self._check(self._L.wig2_batch_step(self._h, int(n)), "wig2_batch_step")
