@@ -179,6 +179,21 @@ int wig2_observables(wig2_ctx* ctx, wig2_obs* obs, double* n1, double* n12, doub
 int wig2_theta(wig2_ctx* ctx, const void* in_dev, void* out_dev);
 int wig2_advect(wig2_ctx* ctx, int32_t dim, double s, const void* in_dev, void* out_dev);
 
+/* Allocation-free variant of wig2_advect, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, result and stream as wig2_advect.
+ * Where wig2_advect lazily allocates a state-sized coefficient buffer (the
+ * general sweep: displacements of more than one cell, or an nx without a
+ * register-resident sweep), this call uses a static device array of 64 MiB
+ * instead, one per device, held until the process ends; it calls no
+ * hipMalloc / hipFree.  Sweeps that need the buffer are rejected with
+ * WIG2_EINVAL when nx*nx*nk*nk*elem_bytes exceeds 64 MiB; register-resident
+ * sweeps need no buffer and have no size limit.  All calls on one device
+ * share that array: calls that overlap in time on one device (other streams,
+ * other contexts, other host threads) race and must be serialised by the
+ * caller.  The array's contents are not meaningful between calls. */
+int wig2_advect_noalloc(wig2_ctx* ctx, int32_t dim, double s, const void* in_dev, void* out_dev);
+
 /* Per-kernel-class timing of wig2_step with HIP events on the context stream
  * (a tracing aid; adds two event records per launch while enabled).
  * wig2_profile_read synchronises, then fills ms[WIG2_PROF_N] (total

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -12,6 +13,42 @@
 #include "common.h"
 
 using namespace wig2;
+
+// Scratch of the allocation-free sweep (wig2_advect_noalloc): the spline
+// coefficients of the general sweep, laid out like the state, for states of
+// at most kNoAllocScratchBytes.  Every device the library runs on holds its
+// own copy until the process ends.  Host code never passes `scratch` itself
+// to a kernel: it passes the device address that hipGetSymbolAddress returns
+// for the current device (noalloc_scratch).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device), resolved
+// once per device.  Called from wig2_create.
+hipError_t resolve_noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void* noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+}  // namespace
 
 struct wig2_ctx {
     GridInfo g{};
@@ -662,6 +699,7 @@ int wig2_create(const wig2_grid* grid, const wig2_params* prm, void* hip_stream,
         return code;
     };
     if (hipGetDevice(&c->device) != hipSuccess) return bail(WIG2_EDEVICE);
+    if (resolve_noalloc_scratch(c->device) != hipSuccess) return bail(WIG2_EDEVICE);
     if (hip_stream) {
         c->st = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -923,6 +961,30 @@ int wig2_advect(wig2_ctx* c, int32_t dim, double s, const void* in, void* out)
     hipError_t e = c->elem == 8 ? advect<double>(c, dim, s, (const double*)in, (double*)out)
                                 : advect<float>(c, dim, s, (const float*)in, (float*)out);
     if (e != hipSuccess) return fail(c, WIG2_EDEVICE, std::string("advect: ") + hipGetErrorString(e));
+    return WIG2_OK;
+}
+
+int wig2_advect_noalloc(wig2_ctx* c, int32_t dim, double s, const void* in, void* out)
+{
+    if (!c || !in || !out || in == out || (dim != 1 && dim != 2) || !isfin(s)) return WIG2_EINVAL;
+    const double cpp = s / (c->g.mass * c->g.dx());
+    const double maxc = std::fabs(cpp) * c->pmax;
+    void* ws = nullptr;
+    if (!advect_in_registers(c->g.nx, c->g.periodic != 0, maxc)) {
+        // the general sweep writes every coefficient of a line before it reads
+        // one, so the scratch needs no clearing between calls
+        if ((size_t)c->npts * c->elem > kNoAllocScratchBytes)
+            return fail(c, WIG2_EINVAL, "advect_noalloc: this sweep needs a coefficient buffer of the "
+                                        "state's size, larger than the 64 MiB static scratch");
+        ws = noalloc_scratch(c->device);
+        if (!ws) return fail(c, WIG2_ESTATE, "advect_noalloc: scratch address not resolved on this device");
+    }
+    hipError_t e = c->elem == 8
+                       ? launch_advect<double>((const double*)in, (double*)out, (double*)ws, c->g.nx, c->g.nk,
+                                               dim, c->g.periodic != 0, cpp, maxc, c->p_d, c->thomas_d, c->st)
+                       : launch_advect<float>((const float*)in, (float*)out, (float*)ws, c->g.nx, c->g.nk,
+                                              dim, c->g.periodic != 0, cpp, maxc, c->p_d, c->thomas_d, c->st);
+    if (e != hipSuccess) return fail(c, WIG2_EDEVICE, "advect_noalloc: launch failed");
     return WIG2_OK;
 }
 

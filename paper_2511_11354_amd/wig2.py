@@ -70,6 +70,7 @@ SIGNATURES = {
     "wig2_observables": ([_vp, ctypes.POINTER(Obs), _dp, _dp, _dp], ctypes.c_int),
     "wig2_theta": ([_vp, _vp, _vp], ctypes.c_int),
     "wig2_advect": ([_vp, ctypes.c_int32, ctypes.c_double, _vp, _vp], ctypes.c_int),
+    "wig2_advect_noalloc": ([_vp, ctypes.c_int32, ctypes.c_double, _vp, _vp], ctypes.c_int),
     "wig2_nodes": ([_vp, _dp, _dp, _dp], ctypes.c_int),
     "wig2_profile": ([_vp, ctypes.c_int32], ctypes.c_int),
     "wig2_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32], ctypes.c_int),
@@ -250,6 +251,11 @@ class Solver:
     def advect(self, dim, s, f_in, f_out):
         self._check(self._L.wig2_advect(self._h, int(dim), float(s), _dev(f_in), _dev(f_out)),
                     "wig2_advect")
+
+    def advect_noalloc(self, dim, s, f_in, f_out):
+        """wig2_advect without device allocation (static per-device scratch)."""
+        self._check(self._L.wig2_advect_noalloc(self._h, int(dim), float(s), _dev(f_in), _dev(f_out)),
+                    "wig2_advect_noalloc")
 
     def profile(self, enable=True):
         self._check(self._L.wig2_profile(self._h, int(enable)), "wig2_profile")
