@@ -247,6 +247,7 @@ hipError_t theta(wig2_ctx* c, const T* u, const T* v, T* out, int mode, double t
 bool use_stream(wig2_ctx* c)
 {
     if (c->theta_path == WIG2_THETA_GENERAL || !theta_stream_ok(theta_args(c))) return false;
+    if (c->prm.precision == WIG2_BF16X2) return true;  // split-BF16 streaming kernel
     return c->theta_path == WIG2_THETA_STREAM || theta_stream_preferred(c->g.nk, c->elem);
 }
 
@@ -999,8 +1000,8 @@ int wig2_set_theta_path(wig2_ctx* c, int32_t path)
 {
     if (!c || path < WIG2_THETA_AUTO || path > WIG2_THETA_STREAM) return WIG2_EINVAL;
     if (path == WIG2_THETA_STREAM && c->has_pot && !theta_stream_ok(theta_args(c)))
-        return fail(c, WIG2_ENOTSUP, "streaming Theta needs a torus, FP64/FP32, nk in {32,48,64,96,128} "
-                                     "and a single-body band of at most 4 modes");
+        return fail(c, WIG2_ENOTSUP, "streaming Theta needs a torus, nk in {32,48,64,96,128} (BF16X2: "
+                                     "{32,64,96,128}) and a single-body band of at most 4 modes");
     c->theta_path = path;
     return WIG2_OK;
 }

@@ -91,6 +91,12 @@ template <typename T>
 hipError_t launch_theta_stream(const ThetaArgs& a, const T* x, const T* y, T* out, int form,
                                double tau, hipStream_t st);
 
+// Split-BF16 streaming Theta (theta_stream_bf16.hip), FP32 state, torus,
+// single-body band <= kStreamBand, nk in {32, 64, 96, 128}; forms as above.
+bool theta_stream_bf16_ok(const ThetaArgs& a);
+hipError_t launch_theta_stream_bf16(const ThetaArgs& a, const float* x, const float* y, float* out, int form,
+                                    double tau, hipStream_t st);
+
 // Panel Theta (theta_panel.hip) for box planes of nk = 256 (SEM matrices
 // too large for the one-plane-in-LDS kernel), FP64, FP32 or split-BF16;
 // forms as for the streaming kernel.  x and out must not be the same array

@@ -539,6 +539,7 @@ hipError_t go_stream_batch(T* pool, const BatchInst* insts, const ThItem* items,
 
 bool theta_stream_ok(const ThetaArgs& a)
 {
+    if (a.precision == WIG2_BF16X2) return theta_stream_bf16_ok(a);
     // (FP32 at nk = 96 spills registers; the general kernel is faster there)
     const bool nk_ok = a.nk == 32 || a.nk == 48 || a.nk == 64 || a.nk == 128 ||
                        (a.nk == 96 && a.precision == WIG2_FP64);
@@ -551,6 +552,12 @@ hipError_t launch_theta_stream(const ThetaArgs& a, const T* x, const T* y, T* ou
                                double tau, hipStream_t st)
 {
     if (!theta_stream_ok(a) || (form == 2 && !y)) return hipErrorNotSupported;
+    if (a.precision == WIG2_BF16X2) {
+        if constexpr (sizeof(T) == 4)
+            return launch_theta_stream_bf16(a, x, y, out, form, tau, st);
+        else
+            return hipErrorNotSupported;
+    }
     switch (a.nk) {
     case 32: return go_stream_nk<T, 32>(a, x, y, out, form, tau, st);
     case 48: return go_stream_nk<T, 48>(a, x, y, out, form, tau, st);

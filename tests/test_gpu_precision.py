@@ -57,8 +57,8 @@ def runs():
 @pytest.mark.parametrize("prec,tol_drift,tol_n1,tol_n12", [
     ("fp32", 5e-8, 5e-7, 1e-6),
     pytest.param("bf16x2", 5e-8, 1e-6, 1e-6, marks=pytest.mark.xfail(
-        reason="split-BF16 on the general kernel misses the 1e-6 pair-density bound "
-               "(measured 9.9e-7 here, 1.9e-6 after 1000 steps at 128^4)", strict=False)),
+        reason="split-BF16 is at the 1e-6 pair-density bound here and misses it after 1000 "
+               "steps at 128^4 (1.2e-6 against FP64; FP32 9.9e-7)", strict=False)),
 ])
 def test_reduced_precision_400_steps(runs, prec, tol_drift, tol_n1, tol_n12):
     (r0, r1), (o0, o1) = runs["fp64"], runs[prec]
