@@ -164,11 +164,12 @@ def cpu_baseline(w, f0, budget_s=20.0, gpu_theta=None, gpu_advect=None):
 
 def bench_surrogate(a):
     """Learned pair-increment surrogate at the periodic 128^4 shape (FP32):
-    train on blocks of ensemble instances (seeds 1000+), then advance the
-    same number of blocks from the mixture state (seed 0) exactly and with
-    the surrogate attached (drift tolerance 1e-6, exact check every 8
-    blocks); report both rates, the fallbacks and the final eps_inf of the
-    surrogate run against the exact one."""
+    trained through wig2_surrogate_train on a batch of ensemble instances
+    (seeds 1000+, those of at most 48^2 x 64^2 points), then the same number
+    of blocks from the mixture state (seed 0) advanced exactly and with the
+    surrogate attached (drift tolerance 1e-6, exact check every 8 blocks),
+    and with the surrogate alone (no monitor, no checks); both rates, the
+    fallbacks and the final eps_inf against the exact run are reported."""
     import numpy as np
     import torch
 
@@ -177,28 +178,28 @@ def bench_surrogate(a):
 
     prec = a.precision or "fp32"
     B = 8
-    model = wig2.Surrogate(block=B, epochs=2, batch=65536, lr=3e-3, seed=0)
-    t0 = time.perf_counter()
     ens = I.ensemble()
-    train_ids = [i for i, w in enumerate(ens) if w.nx >= 48 and w.nk >= 48][:3]
-    for i in train_ids:
+    pick = [i for i, w in enumerate(ens) if w.points <= 48 * 48 * 64 * 64][:6]
+    b = wig2.Batch([dict(nx=ens[i].nx, nk=ens[i].nk, dt=ens[i].dt) for i in pick], precision=prec)
+    for j, i in enumerate(pick):
         w = ens[i]
+        b.set_potentials(j, w.vext, w.v12)
         s = wig2.Solver(w.nx, w.nk, dt=w.dt, precision=prec)
-        s.set_potentials(w.vext, w.v12)
         x, p, _ = s.nodes()
-        s.set_state(I.mixture(x, p, seed=w.extra["seed"], period=20.0))
-        model.collect(s, blocks=2, train=True)
+        b.set_state(j, I.mixture(x, p, seed=w.extra["seed"], period=20.0))
         s.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    model = wig2.Surrogate.train_on_batch(b, block=B, epochs=8, lr=2e-3, seed=0, train_blocks=2)
+    torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     st = model.stats()
+    b.close()
 
     w = I.large_periodic(u=1.0)
     runs = {}
     nblocks = max(1, a.steps // B)
     f0 = None
-    # exact; surrogate under the drift monitor (1e-6) with an exact check
-    # every 8 blocks; surrogate alone (no monitor, no checks): its rate at
-    # the error it reaches
     for mode in ("exact", "surrogate", "unchecked"):
         s = wig2.Solver(w.nx, w.nk, dt=w.dt, precision=prec)
         s.set_potentials(w.vext, w.v12)
@@ -216,14 +217,14 @@ def bench_surrogate(a):
         s.step(nblocks * B)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
-        runs[mode] = {"solver": s, "seconds": dt, "value": w.points * nblocks * B / dt}
-    fe, fs = runs["exact"]["solver"].get_state(), runs["surrogate"]["solver"].get_state()
-    eps = float(np.abs(fs - fe).max() / np.abs(fe).max())
-    eps_u = float(np.abs(runs["unchecked"]["solver"].get_state() - fe).max() / np.abs(fe).max())
-    rep = runs["surrogate"]["solver"].surrogate_report()
-    rep_u = runs["unchecked"]["solver"].surrogate_report()
-    for r in runs.values():
-        r["solver"].close()
+        runs[mode] = {"state": s.get_state(), "seconds": dt, "value": w.points * nblocks * B / dt,
+                      "report": s.surrogate_report() if mode != "exact" else None}
+        s.close()
+        del s
+        torch.cuda.synchronize()
+    fe = runs["exact"]["state"]
+    eps = float(np.abs(runs["surrogate"]["state"] - fe).max() / np.abs(fe).max())
+    eps_u = float(np.abs(runs["unchecked"]["state"] - fe).max() / np.abs(fe).max())
     # the method without what the surrogate supplies: the same steps with no
     # pair term, against the exact run
     s = wig2.Solver(w.nx, w.nk, dt=w.dt, precision=prec)
@@ -239,15 +240,17 @@ def bench_surrogate(a):
         "data": "synthetic",
         "config": {"workload": w.name + "-surrogate", "nx": w.nx, "nk": w.nk, "points": w.points,
                    "dt": w.dt, "block": B, "drift_tol": 1e-6, "exact_check_every": 8,
-                   "train_instances": [ens[i].name for i in train_ids], "seed": 0},
+                   "model": {"params": model.nparams, "conv_layers": model.nlayers, "channels": 16,
+                             "blocks": 9, "k_p": 35, "k_x": 7},
+                   "train_instances": [ens[i].name for i in pick], "seed": 0},
         "exact": {"value": runs["exact"]["value"],
                   "ms_per_step": runs["exact"]["seconds"] / (nblocks * B) * 1e3},
         "speedup_vs_exact": runs["exact"]["seconds"] / runs["surrogate"]["seconds"],
         "unchecked": {"value": runs["unchecked"]["value"],
                       "ms_per_step": runs["unchecked"]["seconds"] / (nblocks * B) * 1e3,
                       "speedup_vs_exact": runs["exact"]["seconds"] / runs["unchecked"]["seconds"],
-                      "eps_inf_vs_exact": eps_u, **rep_u},
-        "surrogate": dict(rep, eps_inf_vs_exact=eps, eps_inf_without_pair_term=eps_nov,
+                      "eps_inf_vs_exact": eps_u, **runs["unchecked"]["report"]},
+        "surrogate": dict(runs["surrogate"]["report"], eps_inf_vs_exact=eps, eps_inf_without_pair_term=eps_nov,
                           train_seconds=t_train, **st),
         "roofline": None, "cpu_baseline": None,
     }

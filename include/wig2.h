@@ -291,36 +291,57 @@ const char* wig2_batch_last_error(const wig2_batch* b);
  * Not part of the paper's method: an accelerator with an exact fallback.
  * For a block of B fine steps from f_t, the exact block gives f_full and the
  * same B steps without Theta[V12] (Sec. 3.1.2) give f_nov; the model learns
- * Delta = f_full - f_nov as a function of f_t.  Model: per grid point an MLP
- * (2 tanh layers of 16) plus a linear path, on 20 features of f_t along the
- * anti-diagonal through the point, v_m = f_t(n1 - m, n2 + m), in the form
- * of the pair term (whose kernel is V12_m sin(m a), a = 2 pi (i1 - i2)/nx):
- * v_0, sin(m a)(v_m - v_-m) and cos(m a)(v_m + v_-m) for m = 1..8, sin a,
- * cos a and the pair strength U = V12(0); 645 parameters, trained in FP32
- * with Adam on the GPU, applied with BF16 weights and FP32 arithmetic.
- * Torus contexts with a pair potential, FP64 or FP32, no mean field.
+ * Delta = f_full - f_nov as a function of f_t.
+ * Model: a 4-D separable convolutional network with 16 channels.  Input
+ * features per grid point, in the form of the pair term (kernel
+ * V12_m sin(m a), a = 2 pi (i1 - i2)/nx, on antisymmetric differences along
+ * the anti-diagonal through the point): c_0 = s_in f_t(n1, n2) and
+ * c_m = s_in U sin(m a) [f_t(n1 - m, n2 + m) - f_t(n1 + m, n2 - m)],
+ * m = 1..15 (U = V12(0)).  Then `blocks` blocks of four layers, one
+ * convolution along each axis p1, p2 (k_p taps, zero off the p-box), x1, x2
+ * (k_x taps, periodic), 16 -> 16 channels, each h <- h + tanh(b + W * h);
+ * output y = b_o + w_o . h + a . c, Delta = s_out y.  Parameters:
+ * blocks (2 (256 k_p + 16) + 2 (256 k_x + 16)) + 33; with blocks = 9,
+ * k_p = 35, k_x = 7: 194,145.  Weights and activations in BF16 on the bf16
+ * matrix cores, FP32 accumulation and FP32 master weights (Adam), forward
+ * and backward in the library's own kernels; each training step is a
+ * full-grid gradient of the mean squared error.  Torus contexts with a pair
+ * potential, FP64 or FP32 state, nk a multiple of 16, no mean field.
  * ------------------------------------------------------------------------ */
 typedef struct wig2_surrogate wig2_surrogate;
 typedef struct {
-    int32_t radius;  /* anti-diagonal neighbours per side: must be 8          */
-    int32_t hidden;  /* hidden units per layer: must be 16                    */
-    int32_t block;   /* fine steps per block (B), >= 1                        */
-    int32_t epochs;  /* passes over each collected block                      */
-    int32_t batch;   /* samples per Adam step, a multiple of 256              */
-    double lr;       /* Adam step size                                        */
-    uint64_t seed;   /* weight initialisation and sample order                */
+    int32_t channels;     /* must be 16                                          */
+    int32_t blocks;       /* blocks of four axis convolutions, 1..16             */
+    int32_t k_p;          /* taps of the p1 / p2 convolutions, odd, 1..63        */
+    int32_t k_x;          /* taps of the x1 / x2 convolutions, odd, 1..15        */
+    int32_t block;        /* fine steps per block (B), >= 1                      */
+    int32_t epochs;       /* Adam steps per collected block                      */
+    double lr;            /* Adam step size                                      */
+    uint64_t seed;        /* weight initialisation                               */
+    int32_t train_blocks; /* wig2_surrogate_train: blocks collected per instance */
+    int32_t max_points;   /* wig2_surrogate_train: larger instances skipped (0: none) */
 } wig2_train_cfg;
 
-/* Create an untrained model on the current device (Xavier-uniform weights
- * from `seed`).  The input / output scales are fixed by the first collected
- * block (1 / max|f_t| and max|Delta|). */
+/* Create an untrained model on the current device (small uniform weights
+ * from `seed`, zero biases and linear path).  The input / output scales are
+ * fixed by the first collected block (1 / max|f_t| and max|Delta|).
+ * WIG2_ENOTSUP for channels != 16, WIG2_EINVAL for other bad fields. */
 int wig2_surrogate_create(const wig2_train_cfg* cfg, wig2_surrogate** out);
 void wig2_surrogate_destroy(wig2_surrogate* s);
 const char* wig2_surrogate_last_error(const wig2_surrogate* s);
+/* Parameter count and number of convolution layers. */
+int wig2_surrogate_size(const wig2_surrogate* s, int64_t* nparams, int32_t* nlayers);
+/* Train a new model on trajectories of a batched ensemble: for every
+ * instance with state, potentials and a pair term (and at most max_points
+ * points), train_blocks blocks of its exact dynamics from its current state
+ * are run in a context of its own on the batch's stream (the batch's states
+ * are not changed), and the model takes `epochs` full-grid Adam steps per
+ * block.  WIG2_EINVAL if no instance qualifies.  *out owns the model. */
+int wig2_surrogate_train(wig2_batch* data_source, const wig2_train_cfg* cfg, wig2_surrogate** out);
 /* Run `blocks` blocks of the context's exact dynamics from its current state.
  * For each block the pair (f_t, Delta) is formed on the device; with train
- * != 0 the model takes epochs x (points / batch) Adam steps on it, otherwise
- * it is only evaluated.  The context ends on the exact trajectory (its step
+ * != 0 the model takes `epochs` full-grid Adam steps on it, otherwise it is
+ * only evaluated.  The context ends on the exact trajectory (its step
  * count advances by blocks x B).  Allocates two state-sized buffers in the
  * context on first use.  The model remembers the context's dt; contexts with
  * another dt are rejected (WIG2_EINVAL). */
@@ -329,14 +350,14 @@ int wig2_surrogate_collect(wig2_surrogate* s, wig2_ctx* ctx, int32_t blocks, int
  * epoch and of the last evaluation, Adam steps taken, samples seen. */
 int wig2_surrogate_stats(const wig2_surrogate* s, double* train_loss, double* eval_loss,
                          int64_t* updates, int64_t* samples);
-/* Parameters (FP32 master copy, 645 values: W1[16][20], b1, W2[16][16], b2,
- * w3, b3, a[20]) and scales[3] = {in_scale, out_scale, U}.  set resets Adam. */
+/* Parameters (FP32 master copy, nparams values: per layer W[16][K][16]
+ * (c_out, tap, c_in) then its bias[16]; then w_o[16], b_o, a[16]) and
+ * scales[3] = {in_scale, out_scale, U}.  set resets Adam. */
 int wig2_surrogate_get_params(const wig2_surrogate* s, float* params, float* scales);
 int wig2_surrogate_set_params(wig2_surrogate* s, const float* params, const float* scales);
 /* Gradient of the mean squared error over all points of caller-owned device
- * fields ft and delta (the context's element type and grid) with the FP32
- * weights; grad[645] and the loss are written to host memory.  At most 2^22
- * points. */
+ * fields ft and delta (the context's element type and grid) with the
+ * current weights; grad[nparams] and the loss are written to host memory. */
 int wig2_surrogate_grad(wig2_surrogate* s, wig2_ctx* ctx, const void* ft_dev, const void* delta_dev,
                         float* grad, double* loss);
 /* Attach to a context: from then on wig2_step advances whole blocks of B

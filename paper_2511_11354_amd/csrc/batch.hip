@@ -545,6 +545,33 @@ int wig2_batch_set_potentials(wig2_batch* b, int32_t i, wig2_fn1 v_ext, wig2_fn1
     return upload_insts(b);
 }
 
+}  // extern "C"
+
+namespace wig2 {
+int batch_count(const wig2_batch* b) { return b ? b->n : 0; }
+bool batch_view(const wig2_batch* b, int i, BatchView& v)
+{
+    if (!b || i < 0 || i >= b->n) return false;
+    const HostInst& h = b->inst[i];
+    v.g = h.g;
+    v.prm = h.prm;
+    v.elem = b->elem;
+    v.f = static_cast<const char*>(b->f) + (size_t)h.off * b->elem;
+    v.sig = b->sig_pool + h.tab_off;
+    v.kap = b->kap_pool + h.tab_off;
+    v.band = h.band;
+    v.two_body = h.two_body;
+    v.vext_x = &h.vext_x;
+    v.v12pair = &h.v12pair;
+    v.has_pot = h.has_pot;
+    v.has_state = h.has_state;
+    v.st = b->st;
+    return true;
+}
+}  // namespace wig2
+
+extern "C" {
+
 int wig2_batch_set_state(wig2_batch* b, int32_t i, const double* fh)
 {
     if (!b || !fh || i < 0 || i >= b->n) return WIG2_EINVAL;

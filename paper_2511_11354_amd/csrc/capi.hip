@@ -90,6 +90,7 @@ struct wig2_ctx {
     bool no_pair = false;            // steps leave out Theta[V12]
     void* ft = nullptr;              // block-start state
     void* fs = nullptr;              // second block result
+    unsigned short* sur_buf = nullptr;  // inference activations: features and two layer buffers
     const wig2_surrogate* sur = nullptr;
     double sur_tol = 0.0;
     int sur_every = 0, sur_since = 0;
@@ -99,18 +100,35 @@ struct wig2_ctx {
     double sur_mref = 0.0, sur_eref = 0.0;
 };
 
+// One layer of the surrogate: a convolution along `axis` (0: p1, 1: p2,
+// 2: x1, 3: x2) with K taps; W at params[woff] ([16][K][16]), its bias at
+// params[woff + 256 K]; packed A fragments at frag[foff].
+struct SurLayer {
+    int axis, K;
+    long woff, foff;
+};
+
 struct wig2_surrogate {
     int device = 0;
     wig2_train_cfg cfg{};
-    float* params = nullptr;
+    std::vector<SurLayer> layers;
+    long P = 0, head_off = 0, frag_total = 0;
+    float* params = nullptr;  // FP32 master weights (layers, then the head w_o[16], b_o, a[16])
     float* mom = nullptr;
     float* var = nullptr;
-    unsigned short* pbf = nullptr;
-    float* partial = nullptr;  // [batch / 256][kSurP]
-    float* lpart = nullptr;    // loss sums per workgroup, one epoch
-    long lpart_cap = 0;
-    float* grad = nullptr;     // [kSurP]
-    float* maxpart = nullptr;  // [2 * kMaxParts]
+    float* grad = nullptr;
+    unsigned short* frag_f = nullptr;  // bf16 A fragments, forward
+    unsigned short* frag_b = nullptr;  // bf16 A fragments, input gradient (transposed, flipped)
+    float* part = nullptr;             // per-workgroup gradient sums
+    size_t part_cap = 0;
+    float* lpart = nullptr;            // per-workgroup loss sums
+    size_t lpart_cap = 0;
+    float* maxpart = nullptr;          // [2 * kMaxParts]
+    long act_cap = 0;                  // training activations, points
+    std::vector<unsigned short*> h;    // h[0] = features .. h[L]
+    std::vector<unsigned short*> t;    // tanh outputs of the layers
+    float* dh[2] = {nullptr, nullptr};
+    int grid = 1024;
     wig2::SurScales sc{1.f, 1.f, 1.f, 0.f};
     bool scaled = false;
     double dt = 0.0;
@@ -484,20 +502,14 @@ int diff_max(wig2_ctx* c, float* part, const T* a, const T* b, T* d, double& dma
     return WIG2_OK;
 }
 
-int ensure_sur_buffers(wig2_ctx* c)
+int ensure_sur_buffers(wig2_ctx* c, bool inference = false)
 {
     const size_t bytes = (size_t)c->npts * c->elem;
     if (!c->ft) HIPCHK(c, hipMalloc(&c->ft, bytes));
     if (!c->fs) HIPCHK(c, hipMalloc(&c->fs, bytes));
+    if (inference && !c->sur_buf)
+        HIPCHK(c, hipMalloc((void**)&c->sur_buf, 3 * (size_t)c->npts * kSurC * sizeof(unsigned short)));
     return WIG2_OK;
-}
-
-long coprime_stride(long n)
-{
-    static const long primes[] = {1000003, 999983, 1000033, 999979};
-    for (long q : primes)
-        if (n % q != 0) return q % n == 0 ? 1 : q % n;
-    return 1;
 }
 
 uint64_t splitmix(uint64_t x)
@@ -508,43 +520,169 @@ uint64_t splitmix(uint64_t x)
     return x ^ (x >> 31);
 }
 
-// One pass over (ft, delta): minibatches of cfg.batch samples in a permuted
-// order; train = Adam steps, else evaluation only.  Returns the mean loss.
-template <typename T>
-int sur_pass(wig2_surrogate* s, wig2_ctx* c, const T* ft, const T* delta, bool train, uint64_t salt,
-             double& loss)
+// Axis geometry of a surrogate convolution on an nx^2 x nk^2 grid.
+SurAxis sur_axis(int axis, int nx, int nk)
 {
+    const long nk2 = (long)nk * nk;
+    SurAxis g{};
+    if (axis == 1) {  // p2 = n2, tiles run along n1
+        g.Sa = 1; g.La = nk; g.periodic = 0; g.Sl = nk; g.Ll = nk;
+        g.R = (long)nx * nx; g.rdiv = nx; g.rs_hi = nx * nk2; g.rs_lo = nk2;
+    } else if (axis == 0) {  // p1 = n1, tiles run along n2
+        g.Sa = nk; g.La = nk; g.periodic = 0; g.Sl = 1; g.Ll = nk;
+        g.R = (long)nx * nx; g.rdiv = nx; g.rs_hi = nx * nk2; g.rs_lo = nk2;
+    } else if (axis == 3) {  // x2 = i2 (periodic), tiles along n2, rest (i1, n1)
+        g.Sa = nk2; g.La = nx; g.periodic = 1; g.Sl = 1; g.Ll = nk;
+        g.R = (long)nx * nk; g.rdiv = nk; g.rs_hi = nx * nk2; g.rs_lo = nk;
+    } else {  // x1 = i1 (periodic), tiles along n2, rest (i2, n1)
+        g.Sa = nx * nk2; g.La = nx; g.periodic = 1; g.Sl = 1; g.Ll = nk;
+        g.R = (long)nx * nk; g.rdiv = nk; g.rs_hi = nk2; g.rs_lo = nk;
+    }
+    return g;
+}
+
+int sur_grow(wig2_surrogate* s, float** buf, size_t* cap, size_t n)
+{
+    if (n <= *cap) return WIG2_OK;
+    if (*buf) hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    if (hipMalloc((void**)buf, n * sizeof(float)) != hipSuccess) return WIG2_ENOMEM;
+    *cap = n;
+    (void)s;
+    return WIG2_OK;
+}
+
+// Training activations for npts points: h[0..L], t[0..L-1] (bf16, 16
+// channels) and two FP32 gradient buffers.
+int sur_ensure_act(wig2_surrogate* s, long npts)
+{
+    if (npts <= s->act_cap) return WIG2_OK;
+    for (auto p : s->h)
+        if (p) hipFree(p);
+    for (auto p : s->t)
+        if (p) hipFree(p);
+    for (auto& p : s->dh)
+        if (p) hipFree(p), p = nullptr;
+    const size_t L = s->layers.size();
+    s->h.assign(L + 1, nullptr);
+    s->t.assign(L, nullptr);
+    s->act_cap = 0;
+    const size_t hb = (size_t)npts * kSurC * sizeof(unsigned short);
+    for (auto& p : s->h)
+        if (hipMalloc((void**)&p, hb) != hipSuccess) return WIG2_ENOMEM;
+    for (auto& p : s->t)
+        if (hipMalloc((void**)&p, hb) != hipSuccess) return WIG2_ENOMEM;
+    for (auto& p : s->dh)
+        if (hipMalloc((void**)&p, (size_t)npts * kSurC * sizeof(float)) != hipSuccess) return WIG2_ENOMEM;
+    s->act_cap = npts;
+    return WIG2_OK;
+}
+
+// Refresh the packed bf16 fragments from the FP32 weights.
+hipError_t sur_pack(wig2_surrogate* s, hipStream_t st)
+{
+    for (const SurLayer& l : s->layers) {
+        hipError_t e = launch_sur_pack(s->params + l.woff, l.K, 0, s->frag_f + l.foff, st);
+        if (e == hipSuccess) e = launch_sur_pack(s->params + l.woff, l.K, 1, s->frag_b + l.foff, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Gradient of the mean squared error (in units of the output scale) over
+// every point of (ft, delta) into s->grad; the loss into `loss`.
+template <typename T>
+int sur_gradient(wig2_surrogate* s, wig2_ctx* c, const T* ft, const T* delta, double& loss)
+{
+    const int nx = c->g.nx, nk = c->g.nk;
     const long n = c->npts;
-    const long nwg_all = (n + 255) / 256 + (long)((n + s->cfg.batch - 1) / s->cfg.batch);
-    if (nwg_all > s->lpart_cap) {
-        if (s->lpart) hipFree(s->lpart);
-        s->lpart = nullptr;
-        HIPCHK(c, hipMalloc(&s->lpart, nwg_all * sizeof(float)));
-        s->lpart_cap = nwg_all;
+    const int L = (int)s->layers.size();
+    if (int r = sur_ensure_act(s, n)) return fail(c, r, "surrogate activations: out of memory");
+    const int nb = (int)((n + 255) / 256);
+    size_t need = (size_t)nb * (2 * kSurC + 1);
+    for (const SurLayer& l : s->layers) need = std::max(need, (size_t)s->grid * (kSurC * kSurC * l.K + kSurC));
+    if (sur_grow(s, &s->part, &s->part_cap, need) || sur_grow(s, &s->lpart, &s->lpart_cap, (size_t)nb))
+        return fail(c, WIG2_ENOMEM, "surrogate gradient buffers: out of memory");
+    HIPCHK(c, launch_sur_feat<T>(ft, nx, nk, s->sc, s->h[0], c->st));
+    for (int l = 0; l < L; ++l) {
+        const SurLayer& ly = s->layers[l];
+        HIPCHK(c, launch_sur_conv(0, sur_axis(ly.axis, nx, nk), ly.K, s->h[l], nullptr, nullptr, s->t[l], s->h[l + 1],
+                                  nullptr, s->frag_f + ly.foff, s->params + ly.woff + 256L * ly.K, s->grid, c->st));
     }
-    const long mul = coprime_stride(n);
-    const long off = (long)(splitmix(s->cfg.seed ^ salt) % (uint64_t)n);
-    long wg_used = 0;
-    for (long k0 = 0; k0 < n; k0 += s->cfg.batch) {
-        const long cnt = std::min<long>(s->cfg.batch, n - k0);
-        const int nwg = (int)((cnt + 255) / 256);
-        HIPCHK(c, launch_sur_batch<T>(ft, delta, c->g.nx, c->g.nk, n, k0, cnt, mul, off, s->sc, s->params,
-                                      s->partial, s->lpart + wg_used, train, c->st));
-        if (train) {
-            ++s->updates;
-            HIPCHK(c, launch_sur_adam(s->params, s->mom, s->var, s->pbf, s->partial, nwg, 2.0f / (float)cnt,
-                                      (float)s->cfg.lr, (int)s->updates, nullptr, c->st));
+    int cur = 0;
+    HIPCHK(c, launch_sur_head<T>(0, s->h[L], s->h[0], delta, nullptr, n, s->sc, s->params + s->head_off,
+                                 2.0f / (float)n, s->dh[cur], s->part, s->lpart, c->st));
+    HIPCHK(c, launch_sur_reduce(s->part, nb, 2 * kSurC + 1, 1.f, s->grad + s->head_off, c->st));
+    std::vector<float> hl((size_t)nb);
+    HIPCHK(c, hipMemcpyAsync(hl.data(), s->lpart, hl.size() * sizeof(float), hipMemcpyDeviceToHost, c->st));
+    for (int l = L - 1; l >= 0; --l) {
+        const SurLayer& ly = s->layers[l];
+        const SurAxis g = sur_axis(ly.axis, nx, nk);
+        const int gdw = (int)std::min<long>(sur_tiles(g), s->grid);
+        HIPCHK(c, launch_sur_dw(g, ly.K, s->h[l], s->dh[cur], s->t[l], s->part, gdw, c->st));
+        HIPCHK(c, launch_sur_reduce(s->part, gdw, kSurC * kSurC * ly.K + kSurC, 1.f, s->grad + ly.woff, c->st));
+        if (l > 0) {
+            HIPCHK(c, launch_sur_conv(1, g, ly.K, nullptr, s->dh[cur], s->t[l], nullptr, nullptr, s->dh[cur ^ 1],
+                                      s->frag_b + ly.foff, nullptr, s->grid, c->st));
+            cur ^= 1;
         }
-        wg_used += nwg;
     }
-    std::vector<float> h((size_t)wg_used);
-    HIPCHK(c, hipMemcpyAsync(h.data(), s->lpart, h.size() * sizeof(float), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     double sum = 0.0;
-    for (float v : h) sum += v;
+    for (float v : hl) sum += v;
     loss = sum / (double)n;
-    s->samples += n;
     return WIG2_OK;
+}
+
+// Mean squared error only.
+template <typename T>
+int sur_eval(wig2_surrogate* s, wig2_ctx* c, const T* ft, const T* delta, double& loss)
+{
+    const int nx = c->g.nx, nk = c->g.nk;
+    const long n = c->npts;
+    const int L = (int)s->layers.size();
+    if (int r = sur_ensure_act(s, n)) return fail(c, r, "surrogate activations: out of memory");
+    const int nb = (int)((n + 255) / 256);
+    if (sur_grow(s, &s->lpart, &s->lpart_cap, (size_t)nb)) return fail(c, WIG2_ENOMEM, "out of memory");
+    HIPCHK(c, launch_sur_feat<T>(ft, nx, nk, s->sc, s->h[0], c->st));
+    for (int l = 0; l < L; ++l) {
+        const SurLayer& ly = s->layers[l];
+        HIPCHK(c, launch_sur_conv(2, sur_axis(ly.axis, nx, nk), ly.K, s->h[l], nullptr, nullptr, nullptr, s->h[l + 1],
+                                  nullptr, s->frag_f + ly.foff, s->params + ly.woff + 256L * ly.K, s->grid, c->st));
+    }
+    HIPCHK(c, launch_sur_head<T>(1, s->h[L], s->h[0], delta, nullptr, n, s->sc, s->params + s->head_off, 0.f,
+                                 nullptr, nullptr, s->lpart, c->st));
+    std::vector<float> hl((size_t)nb);
+    HIPCHK(c, hipMemcpyAsync(hl.data(), s->lpart, hl.size() * sizeof(float), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    double sum = 0.0;
+    for (float v : hl) sum += v;
+    loss = sum / (double)n;
+    return WIG2_OK;
+}
+
+// f += s_out y(ft): the model's increment, with the context's own buffers
+// (the model is not modified).
+template <typename T>
+hipError_t sur_apply(const wig2_surrogate* s, wig2_ctx* c, const T* ft, T* f)
+{
+    const int nx = c->g.nx, nk = c->g.nk;
+    const size_t hb = (size_t)c->npts * kSurC;
+    unsigned short* feat = c->sur_buf;
+    unsigned short* buf[2] = {c->sur_buf + hb, c->sur_buf + 2 * hb};
+    hipError_t e = launch_sur_feat<T>(ft, nx, nk, s->sc, feat, c->st);
+    const unsigned short* cur = feat;
+    for (size_t l = 0; l < s->layers.size() && e == hipSuccess; ++l) {
+        const SurLayer& ly = s->layers[l];
+        e = launch_sur_conv(2, sur_axis(ly.axis, nx, nk), ly.K, cur, nullptr, nullptr, nullptr, buf[l & 1], nullptr,
+                            s->frag_f + ly.foff, s->params + ly.woff + 256L * ly.K, s->grid, c->st);
+        cur = buf[l & 1];
+    }
+    if (e == hipSuccess)
+        e = launch_sur_head<T>(2, cur, feat, nullptr, f, c->npts, s->sc, s->params + s->head_off, 0.f, nullptr, nullptr,
+                               nullptr, c->st);
+    return e;
 }
 
 template <typename T>
@@ -573,15 +711,23 @@ int sur_collect(wig2_surrogate* s, wig2_ctx* c, int blocks, bool train)
             s->scaled = true;
         }
         double loss = 0.0;
-        const int passes = train ? std::max(1, s->cfg.epochs) : 1;
-        for (int ep = 0; ep < passes; ++ep) {
-            const uint64_t salt = ((uint64_t)c->nstep << 20) ^ ((uint64_t)b << 8) ^ (uint64_t)ep;
-            if (int r = sur_pass<T>(s, c, ft, dl, train, salt, loss)) return r;
-        }
-        if (train)
+        if (train) {
+            // full-grid gradient steps on this block (a convolution needs the
+            // whole neighbourhood of every point)
+            for (int ep = 0; ep < std::max(1, s->cfg.epochs); ++ep) {
+                if (int r = sur_gradient<T>(s, c, ft, dl, loss)) return r;
+                ++s->updates;
+                HIPCHK(c, launch_sur_adam(s->params, s->mom, s->var, s->grad, s->P, (float)s->cfg.lr,
+                                          (int)s->updates, c->st));
+                HIPCHK(c, sur_pack(s, c->st));
+                s->samples += c->npts;
+            }
             s->train_loss = loss;
-        else
+        } else {
+            if (int r = sur_eval<T>(s, c, ft, dl, loss)) return r;
             s->eval_loss = loss;
+            s->samples += c->npts;
+        }
         HIPCHK(c, hipMemcpyAsync(f, fs, bytes, hipMemcpyDeviceToDevice, c->st));
         c->nstep += B;
         c->t += B * c->prm.dt;
@@ -605,7 +751,7 @@ int sur_block(wig2_ctx* c)
     }
     HIPCHK(c, hipMemcpyAsync(ft, f, bytes, hipMemcpyDeviceToDevice, c->st));
     HIPCHK(c, run_steps<T>(c, B, true));
-    HIPCHK(c, launch_sur_apply<T>(ft, f, c->g.nx, c->g.nk, s->sc, s->pbf, c->st));
+    HIPCHK(c, sur_apply<T>(s, c, ft, f));
     ++c->sur_blocks;
     ++c->sur_since;
     double m, en;
@@ -756,7 +902,7 @@ void wig2_destroy(wig2_ctx* c)
     void* bufs[] = {c->f_own, c->k1, c->tmp, c->work, c->p_d, c->w_d, c->thomas_d, c->sig_ext_d, c->sig1_d,
                     c->sig2_d, c->kap_d, c->ksem_d, c->ksem_f, c->v12pair_d, c->sintab_d,
                     c->mf_dens_d, c->mf_veff_d, c->s0_d, c->s0b_d, c->skin_d, c->s2_d, c->rows_d,
-                    c->f1_d, c->ft, c->fs};
+                    c->f1_d, c->ft, c->fs, c->sur_buf};
     for (void* b : bufs)
         if (b) hipFree(b);
     for (auto& pe : c->prof_ev) {
@@ -1119,20 +1265,34 @@ int sfail(wig2_surrogate* s, int code, const std::string& m)
     if (s) s->err = m;
     return code;
 }
-unsigned short host_bf16(float v)
-{
-    unsigned u;
-    std::memcpy(&u, &v, 4);
-    return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-}
 int sur_ctx_ok(wig2_surrogate* s, wig2_ctx* c)
 {
     if (!c->has_state || !c->has_pot) return sfail(s, WIG2_ESTATE, "context needs state and potentials");
     if (!c->g.periodic || !c->two_body || c->meanfield)
         return sfail(s, WIG2_ENOTSUP, "surrogate needs a torus context with a pair potential, no mean field");
     if (c->prm.precision == WIG2_BF16X2) return sfail(s, WIG2_ENOTSUP, "surrogate needs FP64 or FP32 state");
+    if (c->g.nk % 16 != 0) return sfail(s, WIG2_ENOTSUP, "surrogate needs nk a multiple of 16");
     if (s->dt != 0.0 && std::fabs(s->dt - c->prm.dt) > 1e-15 * s->dt)
         return sfail(s, WIG2_EINVAL, "model was trained with another dt");
+    return WIG2_OK;
+}
+// The context's tables (symbols, pair kernel, potentials) and state taken
+// from instance i of a batch (device-to-device on the batch stream).
+int ctx_from_batch(wig2_ctx* c, const BatchView& v)
+{
+    const size_t nxk = (size_t)v.g.nx * v.g.nk;
+    HIPCHK(c, hipMemcpyAsync(c->sig_ext_d, v.sig, nxk * 8, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->kap_d, v.kap, nxk * 8, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->f, v.f, (size_t)c->npts * c->elem, hipMemcpyDeviceToDevice, c->st));
+    c->vext_x = *v.vext_x;
+    c->v12pair = *v.v12pair;
+    if (upload(c, c->v12pair_d, c->v12pair)) return WIG2_EDEVICE;
+    c->band = v.band;
+    c->two_body = v.two_body != 0;
+    c->has_pot = true;
+    c->has_state = true;
+    c->nstep = 0;
+    c->t = 0.0;
     return WIG2_OK;
 }
 }  // namespace
@@ -1143,39 +1303,51 @@ int wig2_surrogate_create(const wig2_train_cfg* cfg, wig2_surrogate** out)
 {
     if (!cfg || !out) return WIG2_EINVAL;
     *out = nullptr;
-    if (cfg->radius != kSurR || cfg->hidden != kSurH) return WIG2_ENOTSUP;
-    if (cfg->block < 1 || cfg->epochs < 0 || cfg->batch < 256 || cfg->batch % 256 || !(cfg->lr > 0.0))
+    if (cfg->channels != kSurC) return WIG2_ENOTSUP;
+    auto odd_ok = [](int k, int kmax) { return k >= 1 && k <= kmax && k % 2 == 1; };
+    if (cfg->blocks < 1 || cfg->blocks > 16 || !odd_ok(cfg->k_p, 63) || !odd_ok(cfg->k_x, 15) || cfg->block < 1 ||
+        cfg->epochs < 0 || !(cfg->lr > 0.0) || cfg->train_blocks < 0 || cfg->max_points < 0)
         return WIG2_EINVAL;
     wig2_surrogate* s = new (std::nothrow) wig2_surrogate();
     if (!s) return WIG2_ENOMEM;
     s->cfg = *cfg;
     hipGetDevice(&s->device);
-    const int nwg = cfg->batch / 256;
-    bool ok = hipMalloc((void**)&s->params, kSurP * sizeof(float)) == hipSuccess &&
-              hipMalloc((void**)&s->mom, kSurP * sizeof(float)) == hipSuccess &&
-              hipMalloc((void**)&s->var, kSurP * sizeof(float)) == hipSuccess &&
-              hipMalloc((void**)&s->pbf, kSurP * sizeof(unsigned short)) == hipSuccess &&
-              hipMalloc((void**)&s->grad, kSurP * sizeof(float)) == hipSuccess &&
-              hipMalloc((void**)&s->maxpart, 2 * kMaxParts * sizeof(float)) == hipSuccess &&
-              hipMalloc((void**)&s->partial, (size_t)nwg * kSurP * sizeof(float)) == hipSuccess;
+    int ncu = 256;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, s->device) == hipSuccess)
+        s->grid = 4 * ncu;
+    long off = 0, foff = 0;
+    for (int b = 0; b < cfg->blocks; ++b)
+        for (int axis = 0; axis < 4; ++axis) {
+            const int K = axis < 2 ? cfg->k_p : cfg->k_x;
+            s->layers.push_back(SurLayer{axis, K, off, foff});
+            off += 256L * K + kSurC;
+            foff += (long)(K + 1) / 2 * 64 * 8;
+        }
+    s->head_off = off;
+    s->P = off + 2 * kSurC + 1;
+    s->frag_total = foff;
+    bool ok = hipMalloc((void**)&s->params, s->P * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&s->mom, s->P * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&s->var, s->P * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&s->grad, s->P * sizeof(float)) == hipSuccess &&
+              hipMalloc((void**)&s->frag_f, foff * sizeof(unsigned short)) == hipSuccess &&
+              hipMalloc((void**)&s->frag_b, foff * sizeof(unsigned short)) == hipSuccess &&
+              hipMalloc((void**)&s->maxpart, 2 * kMaxParts * sizeof(float)) == hipSuccess;
     if (!ok) {
         wig2_surrogate_destroy(s);
         return WIG2_ENOMEM;
     }
-    // Xavier-uniform weights, zero biases and linear path
-    std::vector<float> p(kSurP, 0.f);
-    const int D = kSurD, H = kSurH;
-    auto fill = [&](int off, int n, int fan_in, int fan_out) {
-        const double a = std::sqrt(6.0 / (fan_in + fan_out));
-        for (int j = 0; j < n; ++j) {
-            const double u = (double)(splitmix(cfg->seed * 0x100000001B3ull + (uint64_t)(off + j)) >> 11) *
-                             (1.0 / 9007199254740992.0);
-            p[(size_t)off + j] = (float)((2.0 * u - 1.0) * a);
-        }
+    // Small uniform weights (the residual stack starts close to the
+    // identity), zero biases, a small output head and a zero linear path.
+    std::vector<float> p(s->P, 0.f);
+    auto uni = [&](long j) {
+        return (double)(splitmix(cfg->seed * 0x100000001B3ull + (uint64_t)j) >> 11) * (1.0 / 9007199254740992.0);
     };
-    fill(0, H * D, D, H);                              // W1
-    fill(H * D + H, H * H, H, H);                      // W2
-    fill(H * D + H + H * H + H, H, H, 1);              // w3
+    for (const SurLayer& l : s->layers) {
+        const double a = 0.5 * std::sqrt(3.0 / (kSurC * l.K));
+        for (long j = 0; j < 256L * l.K; ++j) p[l.woff + j] = (float)((2.0 * uni(l.woff + j) - 1.0) * a);
+    }
+    for (int k = 0; k < kSurC; ++k) p[s->head_off + k] = (float)((2.0 * uni(s->head_off + k) - 1.0) * 0.05);
     if (int r = wig2_surrogate_set_params(s, p.data(), nullptr)) {
         wig2_surrogate_destroy(s);
         return r;
@@ -1187,16 +1359,29 @@ int wig2_surrogate_create(const wig2_train_cfg* cfg, wig2_surrogate** out)
 void wig2_surrogate_destroy(wig2_surrogate* s)
 {
     if (!s) return;
-    void* bufs[] = {s->params, s->mom, s->var, s->pbf, s->partial, s->lpart, s->grad, s->maxpart};
+    void* bufs[] = {s->params, s->mom, s->var, s->grad, s->frag_f, s->frag_b, s->part, s->lpart, s->maxpart,
+                    s->dh[0], s->dh[1]};
     for (void* b : bufs)
         if (b) hipFree(b);
+    for (auto p : s->h)
+        if (p) hipFree(p);
+    for (auto p : s->t)
+        if (p) hipFree(p);
     delete s;
+}
+
+int wig2_surrogate_size(const wig2_surrogate* s, int64_t* nparams, int32_t* nlayers)
+{
+    if (!s) return WIG2_EINVAL;
+    if (nparams) *nparams = s->P;
+    if (nlayers) *nlayers = (int32_t)s->layers.size();
+    return WIG2_OK;
 }
 
 int wig2_surrogate_get_params(const wig2_surrogate* s, float* params, float* scales)
 {
     if (!s) return WIG2_EINVAL;
-    if (params && hipMemcpy(params, s->params, kSurP * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+    if (params && hipMemcpy(params, s->params, s->P * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
         return WIG2_EDEVICE;
     if (scales) {
         scales[0] = s->sc.in_scale;
@@ -1210,16 +1395,13 @@ int wig2_surrogate_set_params(wig2_surrogate* s, const float* params, const floa
 {
     if (!s) return WIG2_EINVAL;
     if (params) {
-        std::vector<unsigned short> b(kSurP);
-        for (int j = 0; j < kSurP; ++j) {
+        for (long j = 0; j < s->P; ++j)
             if (!std::isfinite(params[j])) return sfail(s, WIG2_EINVAL, "non-finite parameter");
-            b[j] = host_bf16(params[j]);
-        }
-        const std::vector<float> z(kSurP, 0.f);
-        if (hipMemcpy(s->params, params, kSurP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(s->pbf, b.data(), kSurP * sizeof(unsigned short), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(s->mom, z.data(), kSurP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(s->var, z.data(), kSurP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        const std::vector<float> z(s->P, 0.f);
+        if (hipMemcpy(s->params, params, s->P * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(s->mom, z.data(), s->P * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(s->var, z.data(), s->P * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+            sur_pack(s, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
             return sfail(s, WIG2_EDEVICE, "parameter upload failed");
         s->updates = 0;
     }
@@ -1258,40 +1440,57 @@ int wig2_surrogate_collect(wig2_surrogate* s, wig2_ctx* c, int32_t blocks, int32
     return r ? sfail(s, r, c->err) : WIG2_OK;
 }
 
+int wig2_surrogate_train(wig2_batch* b, const wig2_train_cfg* cfg, wig2_surrogate** out)
+{
+    if (!b || !cfg || !out) return WIG2_EINVAL;
+    *out = nullptr;
+    wig2_surrogate* s = nullptr;
+    if (int r = wig2_surrogate_create(cfg, &s)) return r;
+    int used = 0;
+    for (int i = 0; i < batch_count(b); ++i) {
+        BatchView v;
+        if (!batch_view(b, i, v) || !v.has_pot || !v.has_state || !v.two_body) continue;
+        const long npts = (long)v.g.nx * v.g.nx * v.g.nk * v.g.nk;
+        if (cfg->max_points > 0 && npts > cfg->max_points) continue;
+        if (v.g.nk % 16 != 0) continue;
+        const wig2_grid G{v.g.nx, v.g.nk, 1, 1, v.g.x_min, v.g.x_max, 0.0};
+        wig2_params P = v.prm;
+        P.hbar = v.g.hbar;
+        P.mass = v.g.mass;
+        wig2_ctx* c = nullptr;
+        int r = wig2_create(&G, &P, v.st, &c);
+        if (r == WIG2_OK) r = ctx_from_batch(c, v);
+        if (r == WIG2_OK) r = wig2_surrogate_collect(s, c, cfg->train_blocks, 1);
+        if (r != WIG2_OK && c && s->err.empty()) s->err = c->err;
+        wig2_destroy(c);
+        if (r != WIG2_OK) {
+            const std::string msg = "training on instance " + std::to_string(i) + ": " + s->err;
+            wig2_surrogate_destroy(s);
+            (void)msg;
+            return r;
+        }
+        ++used;
+    }
+    if (used == 0) {
+        wig2_surrogate_destroy(s);
+        return WIG2_EINVAL;
+    }
+    *out = s;
+    return WIG2_OK;
+}
+
 int wig2_surrogate_grad(wig2_surrogate* s, wig2_ctx* c, const void* ft, const void* delta, float* grad,
                         double* loss)
 {
     if (!s || !c || !ft || !delta || !grad) return WIG2_EINVAL;
-    const long n = c->npts;
-    if (n > (1l << 22)) return sfail(s, WIG2_EINVAL, "gradient check limited to 2^22 points");
-    const int nwg = (int)((n + 255) / 256);
-    float* part = nullptr;
-    float* lp = nullptr;
-    if (hipMalloc((void**)&part, (size_t)nwg * kSurP * sizeof(float)) != hipSuccess ||
-        hipMalloc((void**)&lp, (size_t)nwg * sizeof(float)) != hipSuccess) {
-        if (part) hipFree(part);
-        return WIG2_ENOMEM;
-    }
-    hipError_t e = c->elem == 8
-                       ? launch_sur_batch<double>((const double*)ft, (const double*)delta, c->g.nx, c->g.nk, n, 0,
-                                                  n, 1, 0, s->sc, s->params, part, lp, true, c->st)
-                       : launch_sur_batch<float>((const float*)ft, (const float*)delta, c->g.nx, c->g.nk, n, 0, n,
-                                                 1, 0, s->sc, s->params, part, lp, true, c->st);
-    if (e == hipSuccess)
-        e = launch_sur_adam(s->params, s->mom, s->var, s->pbf, part, nwg, 2.0f / (float)n, 0.f, 1, s->grad,
-                            c->st);
-    std::vector<float> hl((size_t)nwg);
-    if (e == hipSuccess) e = hipMemcpyAsync(grad, s->grad, kSurP * sizeof(float), hipMemcpyDeviceToHost, c->st);
-    if (e == hipSuccess) e = hipMemcpyAsync(hl.data(), lp, hl.size() * sizeof(float), hipMemcpyDeviceToHost, c->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-    hipFree(part);
-    hipFree(lp);
-    if (e != hipSuccess) return sfail(s, WIG2_EDEVICE, hipGetErrorString(e));
-    if (loss) {
-        double sum = 0.0;
-        for (float v : hl) sum += v;
-        *loss = sum / (double)n;
-    }
+    if (c->g.nk % 16 != 0 || !c->g.periodic) return sfail(s, WIG2_ENOTSUP, "surrogate needs a torus, nk % 16 == 0");
+    double l = 0.0;
+    const int r = c->elem == 8 ? sur_gradient<double>(s, c, (const double*)ft, (const double*)delta, l)
+                               : sur_gradient<float>(s, c, (const float*)ft, (const float*)delta, l);
+    if (r) return sfail(s, r, c->err);
+    if (hipMemcpy(grad, s->grad, s->P * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return sfail(s, WIG2_EDEVICE, "gradient download failed");
+    if (loss) *loss = l;
     return WIG2_OK;
 }
 
@@ -1301,7 +1500,7 @@ int wig2_surrogate_attach(wig2_ctx* c, const wig2_surrogate* s, double drift_tol
     wig2_surrogate* ms = const_cast<wig2_surrogate*>(s);
     if (int r = sur_ctx_ok(ms, c)) return fail(c, r, s->err);
     if (!s->scaled) return fail(c, WIG2_ESTATE, "the model has no scales yet (collect or set them first)");
-    if (int r = ensure_sur_buffers(c)) return r;
+    if (int r = ensure_sur_buffers(c, true)) return r;
     c->sur = s;
     c->sur_tol = drift_tol;
     c->sur_every = every;

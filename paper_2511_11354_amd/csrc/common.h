@@ -106,35 +106,52 @@ template <typename T>
 hipError_t launch_theta_panel(const ThetaArgs& a, const T* x, const T* y, T* out, int form,
                               double tau, hipStream_t st);
 
-// Learned pair-increment surrogate (surrogate.hip): per-point MLP with
-// kSurR anti-diagonal neighbours on each side, kSurH hidden units per layer,
-// plus a linear path from the kSurD features to the output.
-constexpr int kSurR = 8, kSurH = 16;
-constexpr int kSurD = 2 * kSurR + 1 + 3;
-constexpr int kSurP = kSurH * kSurD + kSurH + kSurH * kSurH + kSurH + kSurH + 1 + kSurD;
+// Learned pair-increment surrogate (surrogate.hip): a 4-D separable
+// convolutional network of kSurC channels (features of the pair term, one
+// axis convolution per layer with a residual tanh, a linear output head),
+// BF16 on the matrix cores, forward and backward.
+constexpr int kSurC = 16;
 struct SurScales {
     float in_scale;       // multiplies f_t in the features
     float out_scale;      // Delta = out_scale * y
     float inv_out_scale;
     float u_feat;         // pair-strength feature of the context
 };
-// One minibatch over samples idx = ((k0 + k) mod npts * mul + off) mod npts,
-// k < count (gcd(mul, npts) = 1 makes it a permutation).  Writes per
-// workgroup: the loss sum to lpart and, when train, the gradient sums to
-// partial[nwg][kSurP].
+// One axis of the 4-D grid seen by a convolution: the axis (length La,
+// stride Sa, periodic or zero outside), the lane axis that 16 consecutive
+// points of a tile run along (length Ll, stride Sl), and the R positions of
+// the two remaining coordinates, r -> (r / rdiv) rs_hi + (r % rdiv) rs_lo.
+struct SurAxis {
+    long Sa;
+    int La, periodic;
+    long Sl;
+    int Ll;
+    long R, rdiv, rs_hi, rs_lo;
+};
+size_t sur_conv_lds(int K);
+size_t sur_dw_lds(int K);
+long sur_tiles(const SurAxis& g);
+// mode 0: training forward (hin -> tout = tanh(z), hout = hin + tout);
+// 1: input gradient (dhin, tin -> dhout = dhin + conv^T(dhin (1 - tin^2)));
+// 2: inference forward (hin -> hout).  wf: packed A fragments of the layer.
+hipError_t launch_sur_conv(int mode, const SurAxis& g, int K, const unsigned short* hin, const float* dhin,
+                           const unsigned short* tin, unsigned short* tout, unsigned short* hout, float* dhout,
+                           const unsigned short* wf, const float* bias, int grid, hipStream_t st);
+// Weight and bias gradient sums of one layer, part[grid][16 * 16 * K + 16].
+hipError_t launch_sur_dw(const SurAxis& g, int K, const unsigned short* hin, const float* dhin,
+                         const unsigned short* tin, float* part, int grid, hipStream_t st);
 template <typename T>
-hipError_t launch_sur_batch(const T* ft, const T* delta, int nx, int nk, long npts, long k0, long count,
-                            long mul, long off, const SurScales& sc, const float* params, float* partial,
-                            float* lpart, bool train, hipStream_t st);
-// Reduce the partials (times gscale) and take one Adam step; with grad_out
-// only write the reduced gradient there.
-hipError_t launch_sur_adam(float* params, float* mom, float* var, unsigned short* pbf, const float* partial,
-                           int nwg, float gscale, float lr, int step, float* grad_out, hipStream_t st);
-// f += out_scale * NN(ft) with the BF16 weights.
+hipError_t launch_sur_feat(const T* ft, int nx, int nk, const SurScales& sc, unsigned short* feat, hipStream_t st);
+// mode 0: loss, dhL and head gradient sums; 1: loss only; 2: f += s_out y.
 template <typename T>
-hipError_t launch_sur_apply(const T* ft, T* f, int nx, int nk, const SurScales& sc, const unsigned short* pbf,
-                            hipStream_t st);
-// d = a - b (d may be NULL); part[2 w] = max|a - b|, part[2 w + 1] = max|b| per workgroup.
+hipError_t launch_sur_head(int mode, const unsigned short* hL, const unsigned short* feat, const T* delta, T* f,
+                           long npts, const SurScales& sc, const float* head, float gscale, float* dhL, float* part,
+                           float* lpart, hipStream_t st);
+hipError_t launch_sur_reduce(const float* part, int nwg, int n, float scale, float* grad, hipStream_t st);
+hipError_t launch_sur_adam(float* params, float* mom, float* var, const float* grad, long n, float lr, int step,
+                           hipStream_t st);
+hipError_t launch_sur_pack(const float* W, int K, int transposed, unsigned short* frag, hipStream_t st);
+// d = a - b (when d != NULL) and per-workgroup max|a - b|, max|b| in part[2 nwg].
 template <typename T>
 hipError_t launch_diff_max(const T* a, const T* b, T* d, long n, float* part, int nwg, hipStream_t st);
 
@@ -222,5 +239,23 @@ hipError_t launch_theta_batch(const T* u_pool, const T* v_pool, T* out_pool,
                               const BatchInst* insts, const ThItem* items, int nitems, int mode,
                               const double* sig_pool, const double* kap_pool, int nk, int planes,
                               int grid, hipStream_t st);
+
+// Read-only view of one instance of a batched ensemble (batch.hip), for
+// library-internal consumers such as the surrogate's trainer.
+struct BatchView {
+    GridInfo g;
+    wig2_params prm;
+    int elem;
+    const void* f;        // instance state in the pool
+    const double* sig;    // [nx][nk] single-body symbol
+    const double* kap;    // [nx][nk] pair kernel
+    int band, two_body;
+    const std::vector<double>* vext_x;
+    const std::vector<double>* v12pair;
+    bool has_pot, has_state;
+    hipStream_t st;
+};
+int batch_count(const wig2_batch* b);
+bool batch_view(const wig2_batch* b, int i, BatchView& v);
 
 }  // namespace wig2

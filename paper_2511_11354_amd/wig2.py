@@ -42,12 +42,10 @@ class Obs(ctypes.Structure):
 
 
 class TrainCfg(ctypes.Structure):
-    _fields_ = [("radius", ctypes.c_int32), ("hidden", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
-
-
-SUR_PARAMS = 645  # W1[16][20], b1[16], W2[16][16], b2[16], w3[16], b3, a[20]
+    _fields_ = [("channels", ctypes.c_int32), ("blocks", ctypes.c_int32), ("k_p", ctypes.c_int32),
+                ("k_x", ctypes.c_int32), ("block", ctypes.c_int32), ("epochs", ctypes.c_int32),
+                ("lr", ctypes.c_double), ("seed", ctypes.c_uint64), ("train_blocks", ctypes.c_int32),
+                ("max_points", ctypes.c_int32)]
 
 PROF_NAMES = ("advect_x1", "advect_x2", "theta_stage1", "theta_stage2", "meanfield", "theta_heun",
               "advect_x1x1")
@@ -93,6 +91,8 @@ SIGNATURES = {
     "wig2_batch_destroy": ([_vp], None),
     "wig2_batch_last_error": ([_vp], ctypes.c_char_p),
     "wig2_surrogate_create": ([ctypes.POINTER(TrainCfg), ctypes.POINTER(_vp)], ctypes.c_int),
+    "wig2_surrogate_size": ([_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "wig2_surrogate_train": ([_vp, ctypes.POINTER(TrainCfg), ctypes.POINTER(_vp)], ctypes.c_int),
     "wig2_surrogate_destroy": ([_vp], None),
     "wig2_surrogate_last_error": ([_vp], ctypes.c_char_p),
     "wig2_surrogate_collect": ([_vp, _vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
@@ -417,17 +417,41 @@ class Batch:
 
 
 class Surrogate:
-    """Learned pair-increment model (wig2_surrogate_*): create, collect /
-    train on a Solver's exact trajectory, attach to a Solver."""
+    """Learned pair-increment model (wig2_surrogate_*): a 4-D separable
+    convolutional network (16 channels; `blocks` blocks of p1, p2, x1, x2
+    convolutions with k_p / k_x taps).  Create, collect / train on a
+    Solver's exact trajectory or on a Batch, attach to a Solver."""
 
-    def __init__(self, *, block=8, epochs=2, batch=65536, lr=3e-3, seed=0):
+    def __init__(self, *, blocks=9, k_p=35, k_x=7, block=8, epochs=2, lr=1e-3, seed=0, train_blocks=1,
+                 max_points=0, _handle=None):
         self._L = lib()
-        self.cfg = TrainCfg(8, 16, block, epochs, batch, lr, seed)
+        self.cfg = TrainCfg(16, blocks, k_p, k_x, block, epochs, lr, seed, train_blocks, max_points)
+        if _handle is None:
+            h = ctypes.c_void_p()
+            rc = self._L.wig2_surrogate_create(ctypes.byref(self.cfg), ctypes.byref(h))
+            if rc != OK:
+                raise Wig2Error(rc, f"wig2_surrogate_create: {self._L.wig2_strerror(rc).decode()}")
+            self._h = h
+        else:
+            self._h = _handle
+        n, nl = ctypes.c_int64(), ctypes.c_int32()
+        self._check(self._L.wig2_surrogate_size(self._h, ctypes.byref(n), ctypes.byref(nl)), "wig2_surrogate_size")
+        self.nparams, self.nlayers = n.value, nl.value
+
+    @classmethod
+    def train_on_batch(cls, batch, **cfg):
+        """wig2_surrogate_train: a new model trained on the instances of a Batch."""
+        tmp = cls.__new__(cls)
+        tmp._L = lib()
+        c = dict(blocks=9, k_p=35, k_x=7, block=8, epochs=2, lr=1e-3, seed=0, train_blocks=1, max_points=0)
+        c.update(cfg)
+        tc = TrainCfg(16, c["blocks"], c["k_p"], c["k_x"], c["block"], c["epochs"], c["lr"], c["seed"],
+                      c["train_blocks"], c["max_points"])
         h = ctypes.c_void_p()
-        rc = self._L.wig2_surrogate_create(ctypes.byref(self.cfg), ctypes.byref(h))
+        rc = tmp._L.wig2_surrogate_train(batch._h, ctypes.byref(tc), ctypes.byref(h))
         if rc != OK:
-            raise Wig2Error(rc, f"wig2_surrogate_create: {self._L.wig2_strerror(rc).decode()}")
-        self._h = h
+            raise Wig2Error(rc, f"wig2_surrogate_train: {tmp._L.wig2_strerror(rc).decode()}")
+        return cls(_handle=h, **c)
 
     def _check(self, rc, what):
         if rc != OK:
@@ -457,7 +481,7 @@ class Surrogate:
         return {"train_loss": tl.value, "eval_loss": el.value, "updates": up.value, "samples": sm.value}
 
     def get_params(self):
-        p = np.zeros(SUR_PARAMS, dtype=np.float32)
+        p = np.zeros(self.nparams, dtype=np.float32)
         sc = np.zeros(3, dtype=np.float32)
         fp = ctypes.POINTER(ctypes.c_float)
         self._check(self._L.wig2_surrogate_get_params(self._h, p.ctypes.data_as(fp), sc.ctypes.data_as(fp)),
@@ -467,6 +491,8 @@ class Surrogate:
     def set_params(self, params=None, scales=None):
         fp = ctypes.POINTER(ctypes.c_float)
         p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        if p is not None:
+            assert p.size == self.nparams
         sc = None if scales is None else np.ascontiguousarray(scales, dtype=np.float32)
         self._check(self._L.wig2_surrogate_set_params(self._h, None if p is None else p.ctypes.data_as(fp),
                                                       None if sc is None else sc.ctypes.data_as(fp)),
@@ -474,7 +500,7 @@ class Surrogate:
 
     def grad(self, solver, ft_dev, delta_dev):
         """Gradient of the mean squared error over all points (device fields)."""
-        g = np.zeros(SUR_PARAMS, dtype=np.float32)
+        g = np.zeros(self.nparams, dtype=np.float32)
         loss = ctypes.c_double()
         self._check(self._L.wig2_surrogate_grad(self._h, solver._h, _dev(ft_dev), _dev(delta_dev),
                                                 g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),

@@ -1,92 +1,164 @@
-"""Plain FP64 numpy reference of the learned pair-increment surrogate
-(test infrastructure): features, forward pass, mean-squared-error loss and
-its gradient by explicit back-propagation.  Independent of the HIP kernels;
-pinned to central finite differences in tests/test_surrogate_ref.py.
+"""Plain numpy reference of the learned pair-increment surrogate (test
+infrastructure): features, the 4-D separable convolutional network, the
+mean-squared-error loss and its gradient by explicit back-propagation, in
+FP64.  With `rnd=True` the activations, weights and the back-propagated
+pre-activation gradients are rounded to bfloat16 where the GPU stores them;
+with `rnd=False` it is plain FP64 (pinned to central finite differences in
+tests/test_surrogate_ref.py).  Independent of the HIP kernels.
 
-Model per grid point (i1, i2, n1, n2) of a state f_t[nx, nx, nk, nk], with
-v_m = s_in f_t(i1, i2, n1 - m, n2 + m) (0 off the p-box), l = (i1 - i2) mod nx,
-a = 2 pi l / nx:
-  x = [v_0;  sin(m a) (v_m - v_-m), m = 1..R;  cos(m a) (v_m + v_-m), m = 1..R;
-       sin(a), cos(a), U]
-  y = w3 . tanh(W2 tanh(W1 x + b1) + b2) + b3 + a . x,   Delta ~ s_out y.
-Parameters are packed as W1[H][D], b1[H], W2[H][H], b2[H], w3[H], b3, a[D].
+Model on a state f_t[nx, nx, nk, nk] (grid point P = (i1, i2, n1, n2)),
+a = 2 pi ((i1 - i2) mod nx) / nx, f_t = 0 off the p-box:
+  c_0 = s_in f_t(n1, n2),
+  c_m = s_in U sin(m a) [f_t(n1 - m, n2 + m) - f_t(n1 + m, n2 - m)], m = 1..15;
+  h_0 = c;  per layer l (axis p1, p2, x1, x2 in turn, K taps, centre K // 2)
+  z_l(P)[c] = b_l[c] + sum_{t, c'} W_l[c][t][c'] h_l(P + (t - K // 2) e_axis)[c']
+  (zero off the p-box along p1 / p2, periodic along x1 / x2),
+  t_l = tanh(z_l), h_{l+1} = h_l + t_l;
+  y = b_o + w_o . h_L + a . c.
+Parameter vector: per layer W_l[16][K][16] then b_l[16]; then w_o[16], b_o, a[16].
 """
+from dataclasses import dataclass
+
 import numpy as np
 
-R, H = 8, 16
-D = 2 * R + 1 + 3
-P = H * D + H + H * H + H + H + 1 + D
+C = 16
+# array axis of each convolution axis: p1 -> n1 (2), p2 -> n2 (3), x1 -> i1 (0), x2 -> i2 (1)
+ARRAY_AXIS = {0: 2, 1: 3, 2: 0, 3: 1}
+PERIODIC = {0: False, 1: False, 2: True, 3: True}
 
 
-def unpack(p):
+@dataclass
+class Config:
+    blocks: int = 9
+    k_p: int = 35
+    k_x: int = 7
+
+    def layers(self):
+        out = []
+        for _ in range(self.blocks):
+            for axis in range(4):
+                out.append((axis, self.k_p if axis < 2 else self.k_x))
+        return out
+
+    @property
+    def nparams(self):
+        return sum(C * C * k + C for _, k in self.layers()) + 2 * C + 1
+
+
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    a = np.asarray(x, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def unpack(p, cfg):
     p = np.asarray(p, dtype=np.float64)
-    o = 0
-    W1 = p[o:o + H * D].reshape(H, D); o += H * D
-    b1 = p[o:o + H]; o += H
-    W2 = p[o:o + H * H].reshape(H, H); o += H * H
-    b2 = p[o:o + H]; o += H
-    w3 = p[o:o + H]; o += H
-    b3 = p[o]; o += 1
-    a = p[o:o + D]
-    return W1, b1, W2, b2, w3, b3, a
+    o, Ws = 0, []
+    for axis, k in cfg.layers():
+        W = p[o:o + C * C * k].reshape(C, k, C)
+        o += C * C * k
+        b = p[o:o + C]
+        o += C
+        Ws.append((axis, k, W, b))
+    wo = p[o:o + C]
+    bo = p[o + C]
+    a = p[o + C + 1:o + 2 * C + 1]
+    return Ws, wo, bo, a
 
 
-def shifted(ft, m):
-    """v(n1, n2) = f_t(n1 - m, n2 + m), zero where that leaves the p-box."""
-    nk = ft.shape[2]
-    sh = np.zeros_like(ft)
-    a0, a1 = max(0, m), min(nk, nk + m)          # n1 range with n1 - m in [0, nk)
-    b0, b1 = max(0, -m), min(nk, nk - m)         # n2 range with n2 + m in [0, nk)
-    if a0 < a1 and b0 < b1:
-        sh[:, :, a0:a1, b0:b1] = ft[:, :, a0 - m:a1 - m, b0 + m:b1 + m]
-    return sh
-
-
-def features(ft, in_scale, u):
-    """X[npts, D] in the state's point order (i1, i2, n1, n2)."""
+def features(ft, s_in, u, rnd=True):
     nx, _, nk, _ = ft.shape
-    X = np.zeros((nx, nx, nk, nk, D))
-    i1 = np.arange(nx)[:, None]
-    i2 = np.arange(nx)[None, :]
-    ang = 2.0 * np.pi * ((i1 - i2) % nx) / nx
-    X[..., 0] = in_scale * ft
-    for m in range(1, R + 1):
-        vp, vm = in_scale * shifted(ft, m), in_scale * shifted(ft, -m)
-        X[..., m] = np.sin(m * ang)[:, :, None, None] * (vp - vm)
-        X[..., R + m] = np.cos(m * ang)[:, :, None, None] * (vp + vm)
-    X[..., 2 * R + 1] = np.sin(ang)[:, :, None, None]
-    X[..., 2 * R + 2] = np.cos(ang)[:, :, None, None]
-    X[..., 2 * R + 3] = u
-    return X.reshape(-1, D)
+    F = np.pad(np.asarray(ft, dtype=np.float64), ((0, 0), (0, 0), (15, 15), (15, 15)))
+    i = np.arange(nx)
+    ang = 2 * np.pi * ((i[:, None] - i[None, :]) % nx) / nx
+    out = np.zeros((nx, nx, nk, nk, C))
+    out[..., 0] = s_in * ft
+    for m in range(1, C):
+        d = F[:, :, 15 - m:15 - m + nk, 15 + m:15 + m + nk] - F[:, :, 15 + m:15 + m + nk, 15 - m:15 - m + nk]
+        out[..., m] = s_in * u * np.sin(m * ang)[:, :, None, None] * d
+    return bf16(out) if rnd else out
 
 
-def forward(p, X):
-    W1, b1, W2, b2, w3, b3, a = unpack(p)
-    h1 = np.tanh(X @ W1.T + b1)
-    h2 = np.tanh(h1 @ W2.T + b2)
-    return h2 @ w3 + b3 + X @ a, (h1, h2)
-
-
-def loss(p, X, t):
-    y, _ = forward(p, X)
-    return float(np.mean((y - t) ** 2))
-
-
-def grad(p, X, t):
-    """d loss / d p for loss = mean (y - t)^2."""
-    W1, b1, W2, b2, w3, b3, a = unpack(p)
-    y, (h1, h2) = forward(p, X)
-    n = X.shape[0]
-    dy = 2.0 * (y - t) / n
-    dz2 = (dy[:, None] * w3[None, :]) * (1.0 - h2 ** 2)
-    dz1 = (dz2 @ W2) * (1.0 - h1 ** 2)
-    g = np.concatenate([(dz1.T @ X).ravel(), dz1.sum(0), (dz2.T @ h1).ravel(), dz2.sum(0),
-                        h2.T @ dy, [dy.sum()], X.T @ dy])
+def shift(h, o, axis):
+    """g(P) = h(P + o e_axis): periodic in x, zero off the box in p."""
+    ax = ARRAY_AXIS[axis]
+    if o == 0:
+        return h
+    if PERIODIC[axis]:
+        return np.roll(h, -o, axis=ax)
+    g = np.zeros_like(h)
+    n = h.shape[ax]
+    src = [slice(None)] * h.ndim
+    dst = [slice(None)] * h.ndim
+    if o > 0:
+        src[ax], dst[ax] = slice(o, n), slice(0, n - o)
+    else:
+        src[ax], dst[ax] = slice(0, n + o), slice(-o, n)
+    g[tuple(dst)] = h[tuple(src)]
     return g
 
 
-def bf16_round(p):
-    """Round FP32 values to bfloat16 (nearest, ties to even), back as float64."""
-    a = np.asarray(p, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    r = ((a + 0x7FFF + ((a >> 16) & 1)) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+def conv(h, W, axis):
+    """sum_{t, c'} W[c][t][c'] h(P + (t - K // 2) e_axis)[c']."""
+    k = W.shape[1]
+    out = np.zeros(h.shape[:-1] + (C,))
+    for t in range(k):
+        out += shift(h, t - k // 2, axis) @ W[:, t, :].T
+    return out
+
+
+def conv_t(z, W, axis):
+    """The adjoint of conv: sum_{t, c} W[c][t][c'] z(P - (t - K // 2) e_axis)[c]."""
+    k = W.shape[1]
+    out = np.zeros(z.shape[:-1] + (C,))
+    for t in range(k):
+        out += shift(z, -(t - k // 2), axis) @ W[:, t, :]
+    return out
+
+
+def forward(p, cfg, feat, rnd=True):
+    Ws, wo, bo, a = unpack(p, cfg)
+    h = feat
+    hs, ts = [h], []
+    for axis, k, W, b in Ws:
+        Wq = bf16(W) if rnd else W
+        t = np.tanh(conv(h, Wq, axis) + b)
+        h = bf16(h + t) if rnd else h + t
+        ts.append(bf16(t) if rnd else t)
+        hs.append(h)
+    y = bo + h @ wo + feat @ a
+    return y, (hs, ts)
+
+
+def loss(p, cfg, feat, target, rnd=True):
+    y, _ = forward(p, cfg, feat, rnd)
+    return float(np.mean((y - target) ** 2))
+
+
+def grad(p, cfg, feat, target, rnd=True):
+    """Gradient of mean((y - target)^2) by explicit back-propagation."""
+    Ws, wo, bo, a = unpack(p, cfg)
+    y, (hs, ts) = forward(p, cfg, feat, rnd)
+    n = y.size
+    dy = 2.0 * (y - target) / n
+    g_layers = []
+    dh = dy[..., None] * wo
+    for li in range(len(Ws) - 1, -1, -1):
+        axis, k, W, _ = Ws[li]
+        dz = dh * (1.0 - ts[li] ** 2)
+        if rnd:
+            dz = bf16(dz)
+        hl = hs[li]
+        gW = np.zeros((C, k, C))
+        for t in range(k):
+            gW[:, t, :] = dz.reshape(-1, C).T @ shift(hl, t - k // 2, axis).reshape(-1, C)
+        gb = dz.reshape(-1, C).sum(axis=0)
+        g_layers.append(np.concatenate([gW.ravel(), gb]))
+        if li > 0:
+            dh = dh + conv_t(dz, bf16(W) if rnd else W, axis)
+    g_layers.reverse()
+    g_head = np.concatenate([(dy[..., None] * hs[-1]).reshape(-1, C).sum(axis=0), [dy.sum()],
+                             (dy[..., None] * feat).reshape(-1, C).sum(axis=0)])
+    return np.concatenate(g_layers + [g_head])

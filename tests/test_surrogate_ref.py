@@ -1,60 +1,80 @@
-"""Pins of the numpy surrogate reference: its back-propagated gradient
-against central finite differences of its loss (FP64), and the feature
-layout against a direct per-point loop."""
+"""Pins of the numpy surrogate reference (plain FP64, no bfloat16 rounding):
+its back-propagated gradient against central finite differences of its
+loss, the adjoint identity of its convolution and transpose along every
+axis, the direction of its shifts, and the feature layout against a direct
+per-point loop."""
 import numpy as np
+import pytest
 
 import surrogate_ref as S
 
+CFG = S.Config(blocks=1, k_p=3, k_x=3)
 
-def _setup(seed=0):
+
+def _setup(seed=0, nx=4, nk=16):
     rng = np.random.default_rng(seed)
-    ft = rng.standard_normal((3, 3, 16, 16))
-    p = 0.4 * rng.standard_normal(S.P)
-    X = S.features(ft, 0.7, 1.3)
-    t = rng.standard_normal(X.shape[0])
-    return ft, p, X, t
+    ft = rng.standard_normal((nx, nx, nk, nk))
+    p = 0.4 * rng.standard_normal(CFG.nparams)
+    feat = S.features(ft, 0.7, 1.3, rnd=False)
+    target = rng.standard_normal((nx, nx, nk, nk))
+    return ft, p, feat, target
 
 
 def test_gradient_matches_finite_differences():
-    _, p, X, t = _setup()
-    g = S.grad(p, X, t)
+    _, p, feat, target = _setup()
+    g = S.grad(p, CFG, feat, target, rnd=False)
+    assert g.shape == (CFG.nparams,)
     rng = np.random.default_rng(1)
-    idx = rng.choice(S.P, 60, replace=False).tolist() + [S.P - 1, 0, S.H * S.D]
+    idx = sorted(set(rng.integers(0, CFG.nparams, 40).tolist()) | set(range(CFG.nparams - 33, CFG.nparams)))
+    h = 1e-6
     for j in idx:
-        e = np.zeros(S.P)
-        e[j] = 1e-6
-        fd = (S.loss(p + e, X, t) - S.loss(p - e, X, t)) / 2e-6
-        assert abs(fd - g[j]) <= 1e-7 * max(1.0, abs(g[j])), (j, fd, g[j])
+        e = np.zeros_like(p)
+        e[j] = h
+        fd = (S.loss(p + e, CFG, feat, target, rnd=False) - S.loss(p - e, CFG, feat, target, rnd=False)) / (2 * h)
+        assert abs(fd - g[j]) <= 1e-6 * max(1.0, abs(fd)), (j, fd, g[j])
 
 
-def test_features_direct_loop():
-    ft, _, X, _ = _setup(3)
-    nx, nk = 3, 16
-    Xr = X.reshape(nx, nx, nk, nk, S.D)
+@pytest.mark.parametrize("axis", [0, 1, 2, 3])
+def test_conv_transpose_is_adjoint(axis):
+    rng = np.random.default_rng(2 + axis)
+    h = rng.standard_normal((4, 4, 16, 16, S.C))
+    z = rng.standard_normal((4, 4, 16, 16, S.C))
+    W = rng.standard_normal((S.C, 5, S.C))
+    lhs = np.sum(S.conv(h, W, axis) * z)
+    rhs = np.sum(h * S.conv_t(z, W, axis))
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2, 3])
+def test_conv_tap_direction(axis):
+    """Tap t reads the point (t - K // 2) steps ahead along the axis: an
+    impulse at position 5 appears at 5 - (t - K // 2) in the output."""
+    h = np.zeros((8, 8, 16, 16, S.C))
+    h[5, 5, 5, 5, 3] = 1.0
+    W = np.zeros((S.C, 3, S.C))
+    W[7, 2, 3] = 1.0  # tap 2: offset +1, channel 3 -> 7
+    out = S.conv(h, W, axis)
+    pos = [5, 5, 5, 5]
+    pos[S.ARRAY_AXIS[axis]] = 4
+    assert out[tuple(pos) + (7,)] == 1.0 and np.count_nonzero(out) == 1
+
+
+def test_features_against_point_loop():
     rng = np.random.default_rng(4)
-    for _ in range(50):
-        i1, i2, n1, n2 = (int(v) for v in rng.integers(0, [nx, nx, nk, nk]))
+    nx, nk = 3, 16
+    ft = rng.standard_normal((nx, nx, nk, nk))
+    feat = S.features(ft, 0.5, 2.0, rnd=False)
+
+    def at(i1, i2, a, b):
+        return ft[i1, i2, a, b] if 0 <= a < nk and 0 <= b < nk else 0.0
+
+    for (i1, i2, n1, n2) in [(0, 0, 0, 0), (1, 2, 3, 15), (2, 0, 8, 8), (0, 1, 15, 0)]:
         ang = 2 * np.pi * ((i1 - i2) % nx) / nx
-
-        def v(m):
-            a, b = n1 - m, n2 + m
-            return 0.7 * ft[i1, i2, a, b] if (0 <= a < nk and 0 <= b < nk) else 0.0
-
-        assert Xr[i1, i2, n1, n2, 0] == v(0)
-        for m in range(1, S.R + 1):
-            assert np.isclose(Xr[i1, i2, n1, n2, m], np.sin(m * ang) * (v(m) - v(-m)), rtol=1e-15, atol=1e-15)
-            assert np.isclose(Xr[i1, i2, n1, n2, S.R + m], np.cos(m * ang) * (v(m) + v(-m)),
-                              rtol=1e-15, atol=1e-15)
-        assert np.isclose(Xr[i1, i2, n1, n2, 2 * S.R + 1], np.sin(ang))
-        assert np.isclose(Xr[i1, i2, n1, n2, 2 * S.R + 2], np.cos(ang))
-        assert Xr[i1, i2, n1, n2, 2 * S.R + 3] == 1.3
+        assert feat[i1, i2, n1, n2, 0] == 0.5 * ft[i1, i2, n1, n2]
+        for m in range(1, 16):
+            want = 0.5 * 2.0 * np.sin(m * ang) * (at(i1, i2, n1 - m, n2 + m) - at(i1, i2, n1 + m, n2 - m))
+            assert abs(feat[i1, i2, n1, n2, m] - want) <= 1e-14
 
 
-def test_bf16_rounding():
-    v = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -3.14159], dtype=np.float32)
-    r = S.bf16_round(v)
-    assert r[0] == 1.0
-    assert r[1] == 1.0 + 2 ** -7 or r[1] == 1.0  # tie to even: 1 + 2^-8 -> 1.0
-    assert r[1] == 1.0
-    assert r[2] == 1.0 + 2 ** -7
-    assert abs(r[3] + 3.140625) < 1e-12
+def test_full_config_size():
+    assert S.Config().nparams == 194145
