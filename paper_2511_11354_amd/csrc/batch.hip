@@ -707,8 +707,10 @@ int wig2_batch_tune(wig2_batch* b, const char* cache_path, int32_t force)
     std::map<std::string, int> cache;
     if (cache_path && *cache_path) cache = read_cache(cache_path);
     auto kp = [&](int nk) { return pre + "/theta/nk" + std::to_string(nk) + "/planes"; };
+    // Theta grids are kept per kernel (streaming or general) of the class
     auto kc = [&](const wig2_batch::Cls& c, const char* what) {
-        return pre + "/" + what + "/nx" + std::to_string(c.nx) + "nk" + std::to_string(c.nk) + "/grid";
+        const std::string kind = std::string(what) == "theta" ? (c.stream ? "stream/" : "general/") : "";
+        return pre + "/" + what + "/" + kind + "nx" + std::to_string(c.nx) + "nk" + std::to_string(c.nk) + "/grid";
     };
     bool have = !force;
     for (auto& c : b->cls)

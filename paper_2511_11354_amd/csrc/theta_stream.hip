@@ -143,6 +143,16 @@ __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl
             // (scalar) tile tests; reads of inactive tiles stay inside the
             // LDS allocation (columns -127 .. 255 of rows 0 .. NK-1) and are
             // not used.
+            // Tiles outside the band of wave w: skipped by a wave-uniform
+            // branch, or (kZeroA) multiplied with a zero A operand.  At the
+            // smaller planes the compiler turns the skip branches into
+            // copies of the whole accumulator set at every join (thousands
+            // of moves, and spills at FP32 nk = 96), which costs more than
+            // the extra products (a wave then issues all (NW + 1) NW tile
+            // steps instead of (2 NW + 1) / (3 NW) of them, 72-83% here);
+            // the operands of a skipped tile are finite LDS values (plane,
+            // zero gaps, kernel table), so 0 * B adds an exact zero.
+            constexpr bool kZeroA = sizeof(T) == 4 ? NK < 128 : NK < 64;
             T a[2], bv[2][NSH];
             auto load = [&](int kb, int buf) {
                 a[buf] = pa[-4 * kb];
@@ -159,8 +169,14 @@ __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl
 #pragma unroll
                     for (int j = 0; j < NSH; ++j) {
                         const int d = w + J0 + j - KB;
-                        if (!tile_ok(j) || d < 0 || d > NW) continue;  // wave-uniform
-                        acc[j] = mma(a[cur], bv[cur][j], acc[j]);
+                        if (!tile_ok(j)) continue;
+                        if constexpr (kZeroA) {
+                            const T as = (d < 0 || d > NW) ? T(0) : a[cur];
+                            acc[j] = mma(as, bv[cur][j], acc[j]);
+                        } else {
+                            if (d < 0 || d > NW) continue;  // wave-uniform
+                            acc[j] = mma(a[cur], bv[cur][j], acc[j]);
+                        }
                     }
                     // keep the scheduler from hoisting further operand
                     // reads of the unrolled loop (register pressure)
@@ -540,9 +556,7 @@ hipError_t go_stream_batch(T* pool, const BatchInst* insts, const ThItem* items,
 bool theta_stream_ok(const ThetaArgs& a)
 {
     if (a.precision == WIG2_BF16X2) return theta_stream_bf16_ok(a);
-    // (FP32 at nk = 96 spills registers; the general kernel is faster there)
-    const bool nk_ok = a.nk == 32 || a.nk == 48 || a.nk == 64 || a.nk == 128 ||
-                       (a.nk == 96 && a.precision == WIG2_FP64);
+    const bool nk_ok = a.nk == 32 || a.nk == 48 || a.nk == 64 || a.nk == 96 || a.nk == 128;
     return nk_ok && !a.ksem && a.band >= 0 && a.band <= kStreamBand &&
            (a.precision == WIG2_FP64 || a.precision == WIG2_FP32);
 }
@@ -570,18 +584,16 @@ hipError_t launch_theta_stream(const ThetaArgs& a, const T* x, const T* y, T* ou
 
 bool batch_stream_nk_ok(int nk, int elem_bytes)
 {
-    return nk == 32 || nk == 48 || nk == 64 || nk == 128 || (nk == 96 && elem_bytes == 8);
+    (void)elem_bytes;
+    return nk == 32 || nk == 48 || nk == 64 || nk == 96 || nk == 128;
 }
 
-// Plane sizes where the streaming kernel beats the general one (measured on
-// MI355X, Strang steps of nk^4 with a one-mode V_ext; FP32 at nk = 48 and 64
-// and FP64 at 48 the general kernel is faster): the one-pass Heun form needs
-// more registers per wave than those planes can afford at the occupancy
-// their LDS footprint would allow.
+// The streaming kernel is the faster one at every plane size it supports
+// (measured on MI355X, Strang steps of nx^2 nk^2 with a one-mode V_ext and
+// the pair term, FP64 and FP32, nk = 32 .. 128: 1.1-1.7x the general kernel).
 bool theta_stream_preferred(int nk, int elem_bytes)
 {
-    if (elem_bytes == 8) return nk == 32 || nk == 64 || nk == 96 || nk == 128;
-    return nk == 32 || nk == 128;
+    return batch_stream_nk_ok(nk, elem_bytes);
 }
 
 template <typename T>
@@ -595,11 +607,7 @@ hipError_t launch_theta_stream_batch(T* pool, const BatchInst* insts, const ThIt
     case 32: return go_stream_batch<T, 32>(pool, insts, items, nitems, sig_pool, kap_pool, grid, st);
     case 48: return go_stream_batch<T, 48>(pool, insts, items, nitems, sig_pool, kap_pool, grid, st);
     case 64: return go_stream_batch<T, 64>(pool, insts, items, nitems, sig_pool, kap_pool, grid, st);
-    case 96:
-        if constexpr (sizeof(T) == 8)
-            return go_stream_batch<T, 96>(pool, insts, items, nitems, sig_pool, kap_pool, grid, st);
-        else
-            return hipErrorInvalidValue;
+    case 96: return go_stream_batch<T, 96>(pool, insts, items, nitems, sig_pool, kap_pool, grid, st);
     case 128: return go_stream_batch<T, 128>(pool, insts, items, nitems, sig_pool, kap_pool, grid, st);
     default: return hipErrorInvalidValue;
     }

@@ -47,9 +47,8 @@ def _build(precision):
 def test_batch_equals_single_instances(precision):
     """Every instance of the batch is bitwise the same instance stepped alone
     (same per-plane and per-line arithmetic, different work distribution):
-    the sizes where the automatic choice is the streaming one-pass Heun
-    kernel (FP64 nk = 32, 64 here) take it in both, the others the general
-    kernel."""
+    the streaming one-pass Heun kernel takes every size here but nk = 16,
+    which takes the general kernel, in both."""
     from paper_2511_11354_amd import wig2
 
     b, pots, states = _build(precision)

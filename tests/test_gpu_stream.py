@@ -110,7 +110,7 @@ def test_stream_tiny_workload_20_steps(orc):
         assert e <= 1e-12
 
 
-@pytest.mark.parametrize("nk", [64, 128])
+@pytest.mark.parametrize("nk", [32, 48, 64, 96, 128])
 def test_stream_fp32(orc, nk):
     nx = 8
     s = solver(nx, nk, "cos", True, precision="fp32", dt=0.005)
@@ -144,12 +144,12 @@ def test_stream_path_selection():
     s2 = wig2.Solver(8, 16, dt=0.01)  # nk = 16: general only
     s2.set_potentials(I.cosine(0.5, 20.0), None)
     assert s2.theta_path() == "general"
-    s3 = wig2.Solver(8, 64, dt=0.01, precision="bf16x2")
+    s3 = wig2.Solver(8, 64, dt=0.01, precision="bf16x2")  # split-BF16 streaming kernel
     s3.set_potentials(I.cosine(0.5, 20.0), None)
-    assert s3.theta_path() == "general"
-    # automatic choice by plane size: FP64 64 and FP32 32, 128 stream, FP32 64 general
-    for prec, nk, want in (("fp64", 64, "stream"), ("fp32", 128, "stream"), ("fp32", 64, "general"),
-                           ("fp32", 32, "stream"), ("fp64", 48, "general")):
+    assert s3.theta_path() == "stream"
+    # automatic choice: the streaming kernel at every plane size it supports
+    for prec, nk, want in (("fp64", 64, "stream"), ("fp32", 128, "stream"), ("fp32", 64, "stream"),
+                           ("fp32", 96, "stream"), ("fp32", 32, "stream"), ("fp64", 48, "stream")):
         s4 = wig2.Solver(4, nk, dt=0.01, precision=prec)
         s4.set_potentials(I.cosine(0.5, 20.0), I.smoothed_coulomb(1.0, 1.0))
         assert s4.theta_path() == want, (prec, nk)
