@@ -11,6 +11,7 @@ Functions follow the paper's sections:
   * symbols sig_m, Vhat_m .............. Sec. 3.1.1 / 3.1.2 (eqs. Hartree_FSM,
                                          two_body_FSM; sign: eq. sWigner)
   * SEM single-body matrix ............. Sec. 3.2.1 (eq. Chebyshev_PDO)
+  * SEM two-body operator .............. Sec. 3.2.2 (Poisson summation, D_V, O tensor)
   * cubic-spline advection ............. Sec. 4.1 (B-splines, A_per, A_nat)
   * Strang / Lawson step ............... Sec. 4.1 (Lawson predictor-corrector)
   * observables, 1-RDM entropy ......... Sec. 2.2, Sec. 5.3, Appendix B
@@ -43,7 +44,7 @@ class Params(ctypes.Structure):
 
 
 class Tables(ctypes.Structure):
-    _fields_ = [("sig_ext", _dp), ("vhat12", _dp), ("K", _dp), ("v12_pair", _dp)]
+    _fields_ = [("sig_ext", _dp), ("vhat12", _dp), ("K", _dp), ("v12_pair", _dp), ("v12_sem", _dp)]
 
 
 def build(force: bool = False) -> str:
@@ -80,6 +81,8 @@ def lib():
                                    _dp, _dp], None),
             "or_theta_dense": ([G, _dp, _dp, ctypes.c_long, ctypes.c_long, _dp, _dp], None),
             "or_sem_kernel": ([G, _dp, _dp], None),
+            "or_sem12_dy": ([G], ctypes.c_double),
+            "or_theta12_sem": ([G, _dp, ctypes.c_long, ctypes.c_long, _dp, _dp], None),
             "or_advect": ([G, ctypes.c_int, ctypes.c_double, ctypes.c_long, ctypes.c_long,
                            _dp, _dp], ctypes.c_int),
             "or_step": ([G, P, T, _dp, ctypes.c_long], ctypes.c_int),
@@ -218,6 +221,28 @@ def sem_kernel(g: Grid, v_x: np.ndarray) -> np.ndarray:
     return K
 
 
+def sem12_dy(g: Grid) -> float:
+    return lib().or_sem12_dy(ctypes.byref(g))
+
+
+def sem12_sample_points(g: Grid) -> np.ndarray:
+    """Arguments l dx + d dy (l in [-(nx-1), nx-1], d in [-(nk-1), nk-1]) at
+    which the two-body SEM operator of the box samples V12."""
+    l = np.arange(-(g.nx - 1), g.nx)[:, None]
+    d = np.arange(-(g.nk - 1), g.nk)[None, :]
+    return l * dx(g) + d * sem12_dy(g)
+
+
+def theta12_sem(g: Grid, v12_tab, f, plane0=0, nplanes=None, out=None):
+    """Box two-body operator (Sec. 3.2.2) on the planes [plane0, plane0 + nplanes)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    np_ = g.nx * g.nx if nplanes is None else nplanes
+    out = _out(f, out)
+    lib().or_theta12_sem(ctypes.byref(g), _p(np.ascontiguousarray(v12_tab, dtype=np.float64)), plane0, np_,
+                         _p(f), _p(out))
+    return out
+
+
 def advect(g: Grid, dim: int, s: float, f: np.ndarray, line0=0, nlines=None, out=None) -> np.ndarray:
     if nlines is None:
         nlines = g.nx * g.nk * g.nk - line0
@@ -243,6 +268,8 @@ def tables(g: Grid, vext=None, v12=None):
         d["K"] = sem_kernel(g, vx)
         d["sig_ext"] = None
         d["vhat12"] = None
+        d["v12_sem"] = (np.ascontiguousarray(np.vectorize(v12)(sem12_sample_points(g)), dtype=np.float64)
+                        if v12 else None)
     r = pair_separations(g)
     d["v12_pair"] = np.ascontiguousarray(np.vectorize(v12)(r) if v12 else np.zeros_like(r))
     d["vext_x"] = np.array([vext(x) for x in xnodes(g)]) if vext else np.zeros(g.nx)
@@ -254,7 +281,7 @@ def step(g: Grid, f: np.ndarray, tb: dict, nsteps: int, dt: float, scheme: str =
          two_body: bool = True) -> np.ndarray:
     out = np.ascontiguousarray(f, dtype=np.float64).copy()
     prm = Params(dt, 0 if scheme == "strang" else 1, lam, int(xc), xc_n0, n_scale, int(two_body))
-    t = Tables(_p(tb["sig_ext"]), _p(tb["vhat12"]), _p(tb["K"]), _p(tb["v12_pair"]))
+    t = Tables(_p(tb["sig_ext"]), _p(tb["vhat12"]), _p(tb["K"]), _p(tb["v12_pair"]), _p(tb.get("v12_sem")))
     rc = lib().or_step(ctypes.byref(g), ctypes.byref(prm), ctypes.byref(t), _p(out), nsteps)
     if rc:
         raise RuntimeError(f"or_step failed ({rc})")

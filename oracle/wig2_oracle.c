@@ -21,6 +21,7 @@
  */
 #include "wig2_oracle.h"
 
+#include <complex.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -431,6 +432,156 @@ void or_sem_kernel(const or_grid* g, const double* v_x, double* K)
     free(w);
 }
 
+/* Spacing of the two-body y-lattice of the box (Sec. 3.2.2): dy = pi hbar / |P|
+ * with |P| = 2 hbar k_max the length of the p-box, so that the y-sums below
+ * are periodic in p with the period |P|. */
+double or_sem12_dy(const or_grid* g) { return OR_PI / (2.0 * g->k_max); }
+
+/* Non-periodic two-body operator Theta_12 by the spectral-element route of
+ * Sec. 3.2.2 (Poisson summation in y, D_V, the two-body tensor
+ * O_{s1 s2 l1 l2}), in the paper's order, with the readings below:
+ *  1. Chebyshev coefficients of f on every cell pair (eq. spectral_representation):
+ *       a_{s1 s2 l1 l2} = sum_{k1,k2} c_{l1 k1} c_{l2 k2} f(p_{s1,k1}, p_{s2,k2}),
+ *       c_{lk} = (2 - delta_l0)/N T_l(eta_k).
+ *  2. The two-body tensor contracted with a,
+ *       Ft(y1, y2) = sum a_{s1 s2 l1 l2} O_{s1 s2 l1 l2}(y1, y2),
+ *       O = prod_{j=1,2} (|P_s|/2) e^{2 i dhat_{s_j} y_j / hbar} O_{l_j}(|P_s| y_j / hbar),
+ *     i.e. the integral of f(p1', p2') e^{2 i (p1' y1 + p2' y2)/hbar} over the
+ *     p-box for the cell-wise interpolant.  The tensor is a product of one
+ *     factor per particle, so the sum is taken one particle at a time.
+ *  3. The potential difference D_V at r = x_i1 - x_i2:
+ *       D(y1, y2) = V12(r + y1 - y2) - V12(r - y1 + y2).
+ *  4. Theta_12(p1, p2) = (dy^2 / (pi^2 hbar^3))
+ *       sum_{y1, y2} Im[ e^{-2 i (p1 y1 + p2 y2)/hbar} D(y1, y2) Ft(y1, y2) ].
+ * Readings (the printed constants of this passage are garbled): with the
+ * kernel e^{2 i p y / hbar} of the two-body tensor, the inverse transform of
+ * the two-body Wigner kernel shifts V12 by the full y (not y/2), and the
+ * prefactor follows from the pseudo-difference form of eq. two_body_FSM
+ * (Theta_12 f = (2/(pi hbar^2)) int Vhat(2p'/hbar) sin(2 p' r / hbar)
+ * f(p1 - p', p2 + p') dp', Vhat the Fourier transform of V12), whose sign
+ * matches the closed form of Sec. 5.1.2.  Lattice: the nk midpoints
+ * y_j = (j + 1/2 - nk/2) dy, j = 0..nk-1, symmetric under y -> -y (the sum is
+ * then real term by term in pairs).
+ * v12_tab[(l + nx - 1)(2 nk - 1) + (d + nk - 1)] = V12(l dx + d dy) for
+ * l in [-(nx-1), nx-1], d in [-(nk-1), nk-1].  out = Theta_12 f on the planes
+ * [plane0, plane0 + nplanes). */
+void or_theta12_sem(const or_grid* g, const double* v12_tab, long plane0, long nplanes,
+                    const double* f, double* out)
+{
+    int nx = g->nx, nk = g->nk, M = g->cells, N = nk / M, ny = nk;
+    double hb = g->hbar, dy = or_sem12_dy(g);
+    double pmax = hb * g->k_max, width = 2.0 * pmax / M;
+    double* p = malloc(sizeof(double) * nk);
+    double* w = malloc(sizeof(double) * nk);
+    or_pnodes(g, p, w);
+    double* y = malloc(sizeof(double) * ny);
+    for (int j = 0; j < ny; ++j) y[j] = (j + 0.5 - 0.5 * ny) * dy;
+    /* c[l][k] */
+    double* cc = malloc(sizeof(double) * N * N);
+    for (int l = 0; l < N; ++l)
+        for (int k = 0; k < N; ++k) {
+            double eta = -cos((2.0 * k + 1.0) * OR_PI / (2.0 * N));
+            cc[l * N + k] = (l == 0 ? 1.0 : 2.0) / N * or_cheb(l, eta);
+        }
+    /* E[j][s N + l] = (|P|/2) e^{2 i dhat_s y_j / hbar} O_l(|P| y_j / hbar) */
+    double complex* E = malloc(sizeof(double complex) * ny * nk);
+    for (int j = 0; j < ny; ++j) {
+        double zeta = width * y[j] / hb;
+        int q = 64;
+        int need = (int)(fabs(zeta) + N + 32);
+        if (need > q) q = need;
+        double* gx = malloc(sizeof(double) * q);
+        double* gw = malloc(sizeof(double) * q);
+        or_gauss_legendre(q, gx, gw);
+        for (int l = 0; l < N; ++l) {
+            double complex O = 0.0;
+            for (int t = 0; t < q; ++t) O += gw[t] * cexp(I * zeta * gx[t]) * or_cheb(l, gx[t]);
+            for (int sc = 0; sc < M; ++sc) {
+                double dhat = -pmax + (sc + 0.5) * width;
+                E[(long)j * nk + sc * N + l] = 0.5 * width * cexp(2.0 * I * dhat * y[j] / hb) * O;
+            }
+        }
+        free(gx);
+        free(gw);
+    }
+    double pref = dy * dy / (OR_PI * OR_PI * hb * hb * hb);
+#pragma omp parallel
+    {
+        double* a = malloc(sizeof(double) * nk * nk);
+        double* t = malloc(sizeof(double) * nk * nk);
+        double complex* T2 = malloc(sizeof(double complex) * nk * ny);
+        double complex* Ft = malloc(sizeof(double complex) * ny * ny);
+        double complex* U = malloc(sizeof(double complex) * nk * ny);
+#pragma omp for
+        for (long pl = plane0; pl < plane0 + nplanes; ++pl) {
+            int i1 = (int)(pl / nx), i2 = (int)(pl % nx);
+            const double* F = f + pl * nk * nk;
+            /* 1. coefficients: along p2 into t, then along p1 into a */
+            for (int n1 = 0; n1 < nk; ++n1)
+                for (int s2 = 0; s2 < M; ++s2)
+                    for (int l2 = 0; l2 < N; ++l2) {
+                        double acc = 0.0;
+                        for (int k2 = 0; k2 < N; ++k2) acc += cc[l2 * N + k2] * F[n1 * nk + s2 * N + k2];
+                        t[n1 * nk + s2 * N + l2] = acc;
+                    }
+            for (int s1 = 0; s1 < M; ++s1)
+                for (int l1 = 0; l1 < N; ++l1)
+                    for (int b = 0; b < nk; ++b) {
+                        double acc = 0.0;
+                        for (int k1 = 0; k1 < N; ++k1) acc += cc[l1 * N + k1] * t[(s1 * N + k1) * nk + b];
+                        a[(s1 * N + l1) * nk + b] = acc;
+                    }
+            /* 2. tensor contraction, particle 2 then particle 1 */
+            for (int al = 0; al < nk; ++al)
+                for (int j2 = 0; j2 < ny; ++j2) {
+                    double complex acc = 0.0;
+                    for (int b = 0; b < nk; ++b) acc += a[al * nk + b] * E[(long)j2 * nk + b];
+                    T2[al * ny + j2] = acc;
+                }
+            for (int j1 = 0; j1 < ny; ++j1)
+                for (int j2 = 0; j2 < ny; ++j2) {
+                    double complex acc = 0.0;
+                    for (int al = 0; al < nk; ++al) acc += E[(long)j1 * nk + al] * T2[al * ny + j2];
+                    Ft[j1 * ny + j2] = acc;
+                }
+            /* 3. times D_V */
+            int l = i1 - i2;
+            const double* vt = v12_tab + (long)(l + nx - 1) * (2 * nk - 1);
+            for (int j1 = 0; j1 < ny; ++j1)
+                for (int j2 = 0; j2 < ny; ++j2) {
+                    int d = j1 - j2;
+                    Ft[j1 * ny + j2] *= vt[d + nk - 1] - vt[-d + nk - 1];
+                }
+            /* 4. back to the momentum nodes, y1 then y2 */
+            for (int n1 = 0; n1 < nk; ++n1)
+                for (int j2 = 0; j2 < ny; ++j2) {
+                    double complex acc = 0.0;
+                    for (int j1 = 0; j1 < ny; ++j1)
+                        acc += cexp(-2.0 * I * p[n1] * y[j1] / hb) * Ft[j1 * ny + j2];
+                    U[n1 * ny + j2] = acc;
+                }
+            double* O = out + pl * nk * nk;
+            for (int n1 = 0; n1 < nk; ++n1)
+                for (int n2 = 0; n2 < nk; ++n2) {
+                    double complex acc = 0.0;
+                    for (int j2 = 0; j2 < ny; ++j2)
+                        acc += U[n1 * ny + j2] * cexp(-2.0 * I * p[n2] * y[j2] / hb);
+                    O[n1 * nk + n2] = pref * cimag(acc);
+                }
+        }
+        free(a);
+        free(t);
+        free(T2);
+        free(Ft);
+        free(U);
+    }
+    free(p);
+    free(w);
+    free(y);
+    free(cc);
+    free(E);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Cubic B-spline advection (Sec. 4.1)                                       */
 /* ------------------------------------------------------------------------ */
@@ -612,8 +763,16 @@ static void or_theta_all(or_ctx* c, const double* f, double* out)
     long np = (long)g->nx * g->nx;
     if (g->periodic)
         or_theta_periodic(g, c->sig1, c->sig2, c->tb->vhat12, c->prm->two_body, 0, np, f, out);
-    else
+    else {
         or_theta_dense(g, c->tb->K, c->tb->K, 0, np, f, out);
+        if (c->prm->two_body && c->tb->v12_sem) {
+            long n = np * g->nk * g->nk;
+            double* t = malloc(sizeof(double) * n);
+            or_theta12_sem(g, c->tb->v12_sem, 0, np, f, t);
+            for (long k = 0; k < n; ++k) out[k] += t[k];
+            free(t);
+        }
+    }
 }
 
 /* A_s = A^{x2}_s A^{x1}_s : x1 sweep first, then x2. */

@@ -40,6 +40,8 @@ typedef struct {
     const double* vhat12;   /* periodic: [nk] Fourier modes of V12                */
     const double* K;        /* non-periodic: [nx][nk][nk] SEM single-body matrix  */
     const double* v12_pair; /* [nx][nx] V12(x_i1 - x_i2) (minimum image if torus) */
+    const double* v12_sem;  /* non-periodic: [2nx-1][2nk-1] V12(l dx + d dy) for the
+                               two-body SEM operator, or NULL (no pair term)       */
 } or_tables;
 
 int    or_num_threads(void);
@@ -61,6 +63,9 @@ void or_theta_periodic(const or_grid* g, const double* sig1, const double* sig2,
 void or_theta_dense(const or_grid* g, const double* K1, const double* K2,
                     long plane0, long nplanes, const double* f, double* out);
 void or_sem_kernel(const or_grid* g, const double* v_x, double* K);
+double or_sem12_dy(const or_grid* g);
+void or_theta12_sem(const or_grid* g, const double* v12_tab, long plane0, long nplanes,
+                    const double* f, double* out);
 
 int  or_advect(const or_grid* g, int dim, double s, long line0, long nlines,
                const double* f, double* out);

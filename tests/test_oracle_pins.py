@@ -331,6 +331,58 @@ def test_p14_sem_single_body_closed_form(orc):
     assert errs[0] > 1e3 * errs[1]
 
 
+@pytest.mark.parametrize("hbar", [1.0, 0.7])
+def test_p15_sem_two_body_closed_form(orc, hbar):
+    """Sec. 3.2.2 (box two-body operator through the y-lattice, D_V and the
+    two-body tensor) on the Sec. 5.1.2 closed form: V12 = H_B e^{-r^2/2},
+    f = pi^-2 e^{-(x1+a)^2 - p1^2 - (x2+b)^2 - p2^2}.  At hbar = 1 the exact
+    operator is the printed sqrt2 H_B/pi^2 e^{-(x1+a)^2-(x2+b)^2-(x1-x2)^2/4}
+    e^{-p1^2-p2^2+(p1-p2)^2/4} sin((x1-x2)(p1-p2)/2); at other hbar it is the
+    Gaussian integral of (2/(pi hbar^2)) int Vhat(2p'/hbar) sin(2p'(x1-x2)/hbar)
+    f(p1-p', p2+p') dp' (the pseudo-difference form of eq. two_body_FSM),
+    which reduces to the printed one at hbar = 1.  Spectral convergence in the
+    nodes per cell down to ~1e-11 pins the y-lattice spacing, the full-y shift
+    of V12, the prefactor's powers of pi and hbar, the sign and the particle
+    roles (a != b)."""
+    a, b, hB = 0.6, -0.4, 1.3
+    errs = []
+    for N in (8, 16):
+        g = orc.grid(7, 8 * N, False, 8, -6.0, 6.0, k_max=8.0 / hbar, hbar=hbar)
+        x = orc.xnodes(g)
+        p, _ = orc.pnodes(g)
+        X1, X2, P1, P2 = _mesh(x, p)
+        f = np.ascontiguousarray(np.pi**-2 * np.exp(-(X1 + a) ** 2 - P1**2 - (X2 + b) ** 2 - P2**2))
+        tab = np.vectorize(I.gaussian_pair(hB))(orc.sem12_sample_points(g))
+        th = orc.theta12_sem(g, tab, f)
+        A, B, C = 2 + 2 / hbar**2, 2 * (P1 - P2), 2 * (X1 - X2) / hbar
+        ex = ((2 / (np.pi * hbar**2)) * hB * math.sqrt(2 * np.pi) * np.pi**-2
+              * np.exp(-(X1 + a) ** 2 - (X2 + b) ** 2 - P1**2 - P2**2)
+              * math.sqrt(np.pi / A) * np.exp((B**2 - C**2) / (4 * A)) * np.sin(B * C / (2 * A)))
+        if hbar == 1.0:
+            printed = (math.sqrt(2) * hB / np.pi**2 * np.exp(-(X1 + a) ** 2 - (X2 + b) ** 2 - (X1 - X2) ** 2 / 4)
+                       * np.exp(-P1**2 - P2**2 + (P1 - P2) ** 2 / 4) * np.sin((X1 - X2) * (P1 - P2) / 2))
+            assert np.abs(printed - ex).max() <= 1e-15
+        assert np.abs(ex).max() > 5e-3
+        errs.append(np.abs(th - ex).max() / np.abs(ex).max())
+    assert errs[0] < 1e-3 and errs[1] < 1e-10 and errs[0] > 1e5 * errs[1], errs
+
+
+def test_sem_two_body_exchange_and_zero(orc):
+    """Exchange symmetry of the box two-body operator (V12 even: swapping the
+    particles, (x1, x2, p1, p2) -> (x2, x1, p2, p1), commutes with it) on a
+    random field, and a constant V12 (D_V = 0) gives zero."""
+    g = orc.grid(5, 32, False, 4, -5.0, 5.0, k_max=6.0)
+    rng = np.random.default_rng(7)
+    f = rng.standard_normal((5, 5, 32, 32))
+    tab = np.vectorize(I.smoothed_coulomb(1.0, 1.0))(orc.sem12_sample_points(g))
+    sw = lambda a: np.ascontiguousarray(a.transpose(1, 0, 3, 2))
+    t1 = orc.theta12_sem(g, tab, f)
+    t2 = orc.theta12_sem(g, tab, sw(f))
+    assert np.abs(t1).max() > 1e-2
+    assert np.abs(sw(t1) - t2).max() <= 1e-12 * np.abs(t1).max()
+    assert np.abs(orc.theta12_sem(g, np.full_like(tab, 0.7), f)).max() <= 1e-15
+
+
 def test_sem_harmonic_is_classical_force(orc):
     """For a quadratic potential the Wigner operator is exactly the classical
     force term V'(x) d/dp f (Sec. 2.3 with V'' ' = 0).  On a box wide enough for
