@@ -117,8 +117,14 @@ int wig2_create(const wig2_grid* grid, const wig2_params* params, void* hip_stre
  * V12 at r_j = -L/2 + j L/(2nk) for its Fourier modes (Sec. 3.1.2, even V12
  * assumed), both at the grid nodes / minimum-image separations for the
  * energy and the Hartree term.  Box: V_ext at the nodes for the SEM operator
- * (Sec. 3.2.1); v12 must be NULL (WIG2_ENOTSUP otherwise).
- * v_ext or v12 NULL means zero. */
+ * (Sec. 3.2.1); V12 at l dx + d dy (|l| < nx, |d| < nk, dy = pi / (2 k_max))
+ * for the two-body SEM operator (Sec. 3.2.2: y-lattice of nk midpoints,
+ * D_V, the two-body tensor), which then joins every Theta application
+ * (24 nk flops per point on the matrix cores; tables of 12 nk^2 values and
+ * workspaces of two chunks of at most 512 MiB plus one state-sized array,
+ * allocated here on the first call with a pair potential).  A box with a
+ * pair potential needs nk a multiple of 32, at most 256 (WIG2_ENOTSUP
+ * otherwise).  v_ext or v12 NULL means zero. */
 int wig2_set_potentials(wig2_ctx* ctx, wig2_fn1 v_ext, wig2_fn1 v12, void* user);
 
 /* Upload / download the state as FP64 host arrays of nx*nx*nk*nk values

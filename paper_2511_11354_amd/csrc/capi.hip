@@ -67,6 +67,14 @@ struct wig2_ctx {
     double *sig_ext_d = nullptr, *sig1_d = nullptr, *sig2_d = nullptr, *kap_d = nullptr;
     double *ksem_d = nullptr, *v12pair_d = nullptr, *sintab_d = nullptr;
     float* ksem_f = nullptr;  // FP32 copy of the SEM matrices (nk = 256, FP32 / BF16X2)
+    // box with a pair potential: the two-body SEM operator's tables (element
+    // type of the state), its per-chunk workspaces and a state-sized
+    // accumulator for calls whose output aliases an input
+    bool sem12 = false;
+    void *s12_wa = nullptr, *s12_wb = nullptr, *s12_wc = nullptr, *s12_wd = nullptr, *s12_dt = nullptr;
+    void *s12_wr = nullptr, *s12_wh = nullptr, *s12_acc = nullptr;
+    long s12_chunk = 0;
+    int ncu = 256;
     double *mf_dens_d = nullptr, *mf_veff_d = nullptr;
     double *s0_d = nullptr, *s0b_d = nullptr, *skin_d = nullptr, *s2_d = nullptr;
     double *rows_d = nullptr, *f1_d = nullptr;
@@ -256,10 +264,46 @@ ThetaArgs theta_args(wig2_ctx* c)
     return a;
 }
 
+// Box with a pair potential: the two-body SEM operator (Sec. 3.2.2) is added
+// to the single-body kernel's result.  `single` writes out = base + alpha
+// Theta_1,2 x with x = u + beta v; this adds alpha Theta_12 x.  When out is
+// neither u nor v the single-body kernel runs first and the last product of
+// every chunk of planes accumulates onto out; otherwise Theta_12 x is formed
+// first (into the accumulator) so that the inputs are read before out is
+// written.
+Sem12Args sem12_args(const wig2_ctx* c)
+{
+    return Sem12Args{c->g.nx, c->g.nk, c->ncu, c->s12_wa, c->s12_wb, c->s12_wc, c->s12_wd, c->s12_dt};
+}
+
+template <typename T, typename F>
+hipError_t with_pair_sem(wig2_ctx* c, const T* u, const T* v, double beta, double alpha, T* out, F&& single)
+{
+    if (!c->sem12 || c->no_pair) return single();
+    const long np = (long)c->g.nx * c->g.nx;
+    const Sem12Args a = sem12_args(c);
+    T* wr = static_cast<T*>(c->s12_wr);
+    T* wh = static_cast<T*>(c->s12_wh);
+    const bool direct = out != u && out != v;
+    T* dst = direct ? out : static_cast<T*>(c->s12_acc);
+    hipError_t e;
+    if (direct && (e = single()) != hipSuccess) return e;
+    for (long p0 = 0; p0 < np; p0 += c->s12_chunk) {
+        const long n = std::min(c->s12_chunk, np - p0);
+        if ((e = launch_sem12_pre<T>(a, u, v, beta, p0, n, wr, wh, c->st)) != hipSuccess) return e;
+        if ((e = launch_sem12_post<T>(a, wr, dst, alpha, direct, p0, n, c->st)) != hipSuccess) return e;
+    }
+    if (direct) return hipSuccess;
+    if ((e = single()) != hipSuccess) return e;
+    return launch_sem12_add<T>(dst, out, c->npts, c->ncu, c->st);
+}
+
+// mode 0: out = Theta u; mode 1: out = u + tau/2 (v + Theta (u + tau v))
 template <typename T>
 hipError_t theta(wig2_ctx* c, const T* u, const T* v, T* out, int mode, double tau)
 {
-    return launch_theta<T>(theta_args(c), u, v, out, mode, tau, c->st);
+    return with_pair_sem<T>(c, u, mode == 1 ? v : nullptr, mode == 1 ? tau : 0.0, mode == 1 ? 0.5 * tau : 1.0, out,
+                            [&] { return launch_theta<T>(theta_args(c), u, v, out, mode, tau, c->st); });
 }
 
 bool use_stream(wig2_ctx* c)
@@ -277,7 +321,11 @@ template <typename T>
 hipError_t theta_form(wig2_ctx* c, const T* x, const T* y, T* out, int form, double tau)
 {
     const ThetaArgs a = theta_args(c);
-    if (theta_panel_ok(a)) return launch_theta_panel<T>(a, x, y, out, form, tau, c->st);
+    if (theta_panel_ok(a)) {
+        const double alpha = form == 0 ? 1.0 : form == 1 ? tau : 0.5 * tau;
+        return with_pair_sem<T>(c, x, nullptr, 0.0, alpha, out,
+                                [&] { return launch_theta_panel<T>(a, x, y, out, form, tau, c->st); });
+    }
     return launch_theta_stream<T>(a, x, y, out, form, tau, c->st);
 }
 
@@ -847,6 +895,8 @@ int wig2_create(const wig2_grid* grid, const wig2_params* prm, void* hip_stream,
     };
     if (hipGetDevice(&c->device) != hipSuccess) return bail(WIG2_EDEVICE);
     if (resolve_noalloc_scratch(c->device) != hipSuccess) return bail(WIG2_EDEVICE);
+    if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess)
+        return bail(WIG2_EDEVICE);
     if (hip_stream) {
         c->st = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -902,7 +952,8 @@ void wig2_destroy(wig2_ctx* c)
     void* bufs[] = {c->f_own, c->k1, c->tmp, c->work, c->p_d, c->w_d, c->thomas_d, c->sig_ext_d, c->sig1_d,
                     c->sig2_d, c->kap_d, c->ksem_d, c->ksem_f, c->v12pair_d, c->sintab_d,
                     c->mf_dens_d, c->mf_veff_d, c->s0_d, c->s0b_d, c->skin_d, c->s2_d, c->rows_d,
-                    c->f1_d, c->ft, c->fs, c->sur_buf};
+                    c->f1_d, c->ft, c->fs, c->sur_buf, c->s12_wa, c->s12_wb, c->s12_wc, c->s12_wd,
+                    c->s12_dt, c->s12_wr, c->s12_wh, c->s12_acc};
     for (void* b : bufs)
         if (b) hipFree(b);
     for (auto& pe : c->prof_ev) {
@@ -914,6 +965,44 @@ void wig2_destroy(wig2_ctx* c)
     delete c;
 }
 
+// Tables of the box two-body operator in the state's element type, and its
+// workspaces: per chunk of planes two buffers of 2 nk^2 elements per plane
+// (chunks of at most 512 MiB each), plus a state-sized accumulator.
+int upload_sem12(wig2_ctx* c, const Sem12Tables& t)
+{
+    HIPCHK(c, hipStreamSynchronize(c->st));  // earlier steps may still read the old tables
+    auto put = [&](void** dst, const std::vector<double>& v) -> int {
+        if (*dst) {
+            hipFree(*dst);
+            *dst = nullptr;
+        }
+        if (hipMalloc(dst, v.size() * c->elem) != hipSuccess) return fail(c, WIG2_ENOMEM, "two-body SEM tables");
+        hipError_t e;
+        if (c->elem == 8) {
+            e = hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+        } else {
+            const std::vector<float> f(v.begin(), v.end());
+            e = hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+        }
+        return e == hipSuccess ? WIG2_OK : fail(c, WIG2_EDEVICE, hipGetErrorString(e));
+    };
+    if (int rc = put(&c->s12_wa, t.wa)) return rc;
+    if (int rc = put(&c->s12_wb, t.wb)) return rc;
+    if (int rc = put(&c->s12_wc, t.wc)) return rc;
+    if (int rc = put(&c->s12_wd, t.wd)) return rc;
+    if (int rc = put(&c->s12_dt, t.dtab)) return rc;
+    if (!c->s12_wr) {
+        const long np = (long)c->g.nx * c->g.nx;
+        const size_t per = (size_t)2 * c->g.nk * c->g.nk * c->elem;
+        c->s12_chunk = std::max<long>(1, std::min<long>(np, (long)((size_t)512 << 20) / (long)per));
+        if (hipMalloc(&c->s12_wr, per * c->s12_chunk) != hipSuccess ||
+            hipMalloc(&c->s12_wh, per * c->s12_chunk) != hipSuccess ||
+            hipMalloc(&c->s12_acc, (size_t)c->npts * c->elem) != hipSuccess)
+            return fail(c, WIG2_ENOMEM, "two-body SEM workspaces");
+    }
+    return WIG2_OK;
+}
+
 int wig2_set_potentials(wig2_ctx* c, wig2_fn1 v_ext, wig2_fn1 v12, void* user)
 {
     if (!c) return WIG2_EINVAL;
@@ -921,7 +1010,8 @@ int wig2_set_potentials(wig2_ctx* c, wig2_fn1 v_ext, wig2_fn1 v12, void* user)
     const int nx = g.nx, nk = g.nk;
     const double L = g.L();
     auto V = [&](wig2_fn1 fn, double x) { return fn ? fn(x, user) : 0.0; };
-    if (!g.periodic && v12) return fail(c, WIG2_ENOTSUP, "pair potential on a box needs the two-body SEM operator");
+    if (!g.periodic && v12 && !sem12_nk_ok(nk))
+        return fail(c, WIG2_ENOTSUP, "pair potential on a box needs nk a multiple of 32, at most 256");
     c->vext_x.resize(nx);
     for (int i = 0; i < nx; ++i) c->vext_x[i] = V(v_ext, c->x[i]);
     c->v12pair.assign((size_t)nx * nx, 0.0);
@@ -968,6 +1058,24 @@ int wig2_set_potentials(wig2_ctx* c, wig2_fn1 v_ext, wig2_fn1 v12, void* user)
         }
         c->two_body = false;
         c->band = nk;
+        c->sem12 = false;
+        if (v12) {
+            // two-body SEM operator: V12 at l dx + d dy, the tables in the
+            // state's element type, workspaces for chunks of planes
+            const int nd = 2 * nk - 1;
+            const double dx = g.dx(), dy = sem12_dy(g);
+            std::vector<double> vs((size_t)(2 * nx - 1) * nd);
+            for (int l = -(nx - 1); l <= nx - 1; ++l)
+                for (int d = -(nk - 1); d <= nk - 1; ++d) {
+                    const double v = V(v12, l * dx + d * dy);
+                    if (!isfin(v)) return fail(c, WIG2_EINVAL, "V12 returned a non-finite value");
+                    vs[(size_t)(l + nx - 1) * nd + d + nk - 1] = v;
+                }
+            Sem12Tables t;
+            host_sem12_tables(g, vs, t);
+            if (int rc = upload_sem12(c, t)) return rc;
+            c->sem12 = true;
+        }
     }
     if (upload(c, c->v12pair_d, c->v12pair)) return WIG2_EDEVICE;
     c->has_pot = true;

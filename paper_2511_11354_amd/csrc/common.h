@@ -36,6 +36,14 @@ void host_pair_kernel(const GridInfo& g, const std::vector<double>& v12_r,
                       std::vector<double>& vhat, std::vector<double>& kap);
 // Box single-body SEM matrices K[i][n][n'] from V at the x nodes.
 void host_sem_matrix(const GridInfo& g, const std::vector<double>& v_x, std::vector<double>& K);
+// Box two-body operator (Sec. 3.2.2): y-lattice spacing dy = pi hbar / |P|
+// (|P| = 2 hbar k_max) and the real operands of its four matrix products
+// (layouts in tables.cpp), from vs[l + nx - 1][d + nk - 1] = V12(l dx + d dy).
+inline double sem12_dy(const GridInfo& g) { return 3.141592653589793238462643383279502884 / (2.0 * g.k_max); }
+struct Sem12Tables {
+    std::vector<double> wa, wb, wc, wd, dtab;
+};
+void host_sem12_tables(const GridInfo& g, const std::vector<double>& vs, Sem12Tables& t);
 // Occupations of the trace-one 1-RDM built from f1 on the even sub-lattice.
 double host_entropy(const GridInfo& g, const std::vector<double>& f1, std::vector<double>& occ);
 
@@ -77,6 +85,27 @@ struct ThetaArgs {
 template <typename T>
 hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, double tau,
                         hipStream_t st);
+
+// Box two-body operator (theta12_sem.hip).  Tables in the state's element
+// type: wa (nk x 2nk), wb (2nk x 2nk), wc (2nk x 2nk), wd (2nk x nk), dtab
+// ((2nx-1) x (2nk-1)).  pre: for the planes [plane0, plane0 + nplanes) of
+// x = u + beta v (v may be NULL), the first three products into the
+// workspaces wr, wh (2 nk^2 elements per plane each); post: the fourth,
+// out = alpha Theta_12 x (accumulate = false) or out += alpha Theta_12 x.
+struct Sem12Args {
+    int nx, nk, ncu;
+    const void *wa, *wb, *wc, *wd, *dtab;
+};
+bool sem12_nk_ok(int nk);
+template <typename T>
+hipError_t launch_sem12_pre(const Sem12Args& a, const T* u, const T* v, double beta, long plane0, long nplanes,
+                            T* wr, T* wh, hipStream_t st);
+template <typename T>
+hipError_t launch_sem12_post(const Sem12Args& a, const T* wr, T* out, double alpha, bool accumulate, long plane0,
+                             long nplanes, hipStream_t st);
+// out[i] += acc[i], i < n
+template <typename T>
+hipError_t launch_sem12_add(const T* acc, T* out, long n, int ncu, hipStream_t st);
 
 // Streaming Theta (theta_stream.hip) for the torus with a single-body band of
 // at most 4 modes, FP64 or FP32, nk in {32, 48, 64, 96, 128}:

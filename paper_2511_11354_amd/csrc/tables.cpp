@@ -210,6 +210,81 @@ void host_sem_matrix(const GridInfo& g, const std::vector<double>& v_x, std::vec
     for (auto& t : th) t.join();
 }
 
+// Box two-body operator (Sec. 3.2.2), host tables.  y-lattice: the nk
+// midpoints y_j = (j + 1/2 - nk/2) dy, dy = pi hbar / |P| (|P| = 2 hbar k_max,
+// the sums over y are then |P|-periodic in p).  Complex
+//   G[y][n] = int_{P_s} e^{2 i p y / hbar} ell_n(p) dp
+//           = (h/2) e^{2 i d_s y / hbar} Q_k(h y / hbar)      (n = s N + k)
+//   B[n][y] = e^{-2 i p_n y / hbar}
+// so that G F G^T is the y-transform of the cell-wise interpolant of a plane F
+// and Im(B H B^T) the back-transform; the real operands of the four matrix
+// products (layouts in theta12_sem.hip):
+//   WA[k][j]      = Re G[j][k],  WA[k][ny + j] = Im G[j][k]            (nk x 2ny)
+//   WB[y][2k]     = Re G[y][k],  WB[y][2k+1] = -Im G[y][k],
+//   WB[ny+y][2k]  = Im G[y][k],  WB[ny+y][2k+1] = Re G[y][k]          (2ny x 2nk)
+//   WC[2n][y]     = Re B[n][y],  WC[2n][ny+y] = -Im B[n][y],
+//   WC[2n+1][y]   = Im B[n][y],  WC[2n+1][ny+y] = Re B[n][y]          (2nk x 2ny)
+//   WD[y][n]      = Im B[n][y],  WD[ny+y][n] = Re B[n][y]              (2ny x nk)
+// and the potential difference, with the constant of the y-sum folded in,
+//   D[l + nx - 1][d + ny - 1] = (dy^2/(pi^2 hbar^3)) (V12(l dx + d dy) - V12(l dx - d dy))
+// from vs[l + nx - 1][d + ny - 1] = V12(l dx + d dy).
+void host_sem12_tables(const GridInfo& g, const std::vector<double>& vs, Sem12Tables& t)
+{
+    const int nx = g.nx, nk = g.nk, ny = g.nk, M = g.cells, N = nk / M;
+    const double hb = g.hbar, pm = hb * g.k_max, h = 2.0 * pm / M;
+    const double dy = sem12_dy(g);
+    std::vector<double> x, p, w, eta, bw;
+    host_nodes(g, x, p, w);
+    cheb_nodes(N, eta, bw);
+    std::vector<cplx> G((size_t)ny * nk), Bm((size_t)nk * ny);
+    for (int j = 0; j < ny; ++j) {
+        const double y = (j + 0.5 - 0.5 * ny) * dy;
+        const double zeta = h * y / hb;
+        const int q = std::max(48, (int)std::ceil(std::fabs(zeta)) + 2 * N + 40);
+        std::vector<double> gx, gw;
+        gauss_legendre(q, gx, gw);
+        for (int k = 0; k < N; ++k) {
+            cplx Qk(0.0, 0.0);
+            for (int tq = 0; tq < q; ++tq) Qk += gw[tq] * cardinal(eta, bw, k, gx[tq]) * std::polar(1.0, zeta * gx[tq]);
+            for (int s = 0; s < M; ++s) {
+                const double ds = -pm + h * (s + 0.5);
+                G[(size_t)j * nk + s * N + k] = 0.5 * h * std::polar(1.0, 2.0 * ds * y / hb) * Qk;
+            }
+        }
+        for (int n = 0; n < nk; ++n) Bm[(size_t)n * ny + j] = std::polar(1.0, -2.0 * p[n] * y / hb);
+    }
+    t.wa.assign((size_t)nk * 2 * ny, 0.0);
+    t.wb.assign((size_t)2 * ny * 2 * nk, 0.0);
+    t.wc.assign((size_t)2 * nk * 2 * ny, 0.0);
+    t.wd.assign((size_t)2 * ny * nk, 0.0);
+    for (int j = 0; j < ny; ++j)
+        for (int k = 0; k < nk; ++k) {
+            const cplx gv = G[(size_t)j * nk + k];
+            t.wa[(size_t)k * 2 * ny + j] = gv.real();
+            t.wa[(size_t)k * 2 * ny + ny + j] = gv.imag();
+            t.wb[(size_t)j * 2 * nk + 2 * k] = gv.real();
+            t.wb[(size_t)j * 2 * nk + 2 * k + 1] = -gv.imag();
+            t.wb[(size_t)(ny + j) * 2 * nk + 2 * k] = gv.imag();
+            t.wb[(size_t)(ny + j) * 2 * nk + 2 * k + 1] = gv.real();
+        }
+    for (int n = 0; n < nk; ++n)
+        for (int j = 0; j < ny; ++j) {
+            const cplx bv = Bm[(size_t)n * ny + j];
+            t.wc[(size_t)2 * n * 2 * ny + j] = bv.real();
+            t.wc[(size_t)2 * n * 2 * ny + ny + j] = -bv.imag();
+            t.wc[(size_t)(2 * n + 1) * 2 * ny + j] = bv.imag();
+            t.wc[(size_t)(2 * n + 1) * 2 * ny + ny + j] = bv.real();
+            t.wd[(size_t)j * nk + n] = bv.imag();
+            t.wd[(size_t)(ny + j) * nk + n] = bv.real();
+        }
+    const double c = dy * dy / (kPi * kPi * hb * hb * hb);
+    const int nd = 2 * ny - 1;
+    t.dtab.assign((size_t)(2 * nx - 1) * nd, 0.0);
+    for (int l = 0; l < 2 * nx - 1; ++l)
+        for (int d = -(ny - 1); d <= ny - 1; ++d)
+            t.dtab[(size_t)l * nd + d + ny - 1] = c * (vs[(size_t)l * nd + d + ny - 1] - vs[(size_t)l * nd - d + ny - 1]);
+}
+
 // 1-RDM from the reduced Wigner function (Appendix B):
 //   rho1(x_{mu-nu}, x_{mu+nu}) = sum_n w_n f1(x_mu, p_n) e^{-2 i p_n nu dx / hbar},
 // on the even sub-lattice (all mid-points on the grid).  Eigenvalues of the
