@@ -213,7 +213,9 @@ enum {
     WIG2_PROF_MEANFIELD = 4,    /* density moments + mean-field symbols     */
     WIG2_PROF_THETA_HEUN = 5,   /* stream, Strang: both Heun stages in one pass */
     WIG2_PROF_ADVECT_X1X1 = 6,  /* Strang: two x1 half-sweeps in one launch     */
-    WIG2_PROF_N = 7
+    WIG2_PROF_PAIR_SEM = 7,     /* box two-body SEM operator (inside the Theta
+                                   stages, which include its time as well)       */
+    WIG2_PROF_N = 8
 };
 int wig2_profile(wig2_ctx* ctx, int32_t enable);
 int wig2_profile_read(wig2_ctx* ctx, double* ms, int64_t* counts, int32_t reset);

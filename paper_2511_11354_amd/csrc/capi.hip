@@ -288,11 +288,16 @@ hipError_t with_pair_sem(wig2_ctx* c, const T* u, const T* v, double beta, doubl
     T* dst = direct ? out : static_cast<T*>(c->s12_acc);
     hipError_t e;
     if (direct && (e = single()) != hipSuccess) return e;
-    for (long p0 = 0; p0 < np; p0 += c->s12_chunk) {
-        const long n = std::min(c->s12_chunk, np - p0);
-        if ((e = launch_sem12_pre<T>(a, u, v, beta, p0, n, wr, wh, c->st)) != hipSuccess) return e;
-        if ((e = launch_sem12_post<T>(a, wr, dst, alpha, direct, p0, n, c->st)) != hipSuccess) return e;
-    }
+    e = timed(c, WIG2_PROF_PAIR_SEM, [&] {
+        for (long p0 = 0; p0 < np; p0 += c->s12_chunk) {
+            const long n = std::min(c->s12_chunk, np - p0);
+            hipError_t e2 = launch_sem12_pre<T>(a, u, v, beta, p0, n, wr, wh, c->st);
+            if (e2 == hipSuccess) e2 = launch_sem12_post<T>(a, wr, dst, alpha, direct, p0, n, c->st);
+            if (e2 != hipSuccess) return e2;
+        }
+        return hipSuccess;
+    });
+    if (e != hipSuccess) return e;
     if (direct) return hipSuccess;
     if ((e = single()) != hipSuccess) return e;
     return launch_sem12_add<T>(dst, out, c->npts, c->ncu, c->st);

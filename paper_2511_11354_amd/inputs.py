@@ -186,13 +186,17 @@ def large_periodic(u: float = 1.0) -> Workload:
                     vext=cosine(0.5, 20.0), v12=smoothed_coulomb(u, 1.0), extra={"U": u})
 
 
-def box_sem(nx=129, cells=16, nodes=16, potential="harmonic") -> Workload:
+def box_sem(nx=129, cells=16, nodes=16, potential="harmonic", pair_u=None) -> Workload:
     """Non-periodic box [-15,15], natural spline, SEM momentum grid on
-    [-10 pi/3, 10 pi/3] with `cells` x `nodes` Chebyshev-Gauss points."""
+    [-10 pi/3, 10 pi/3] with `cells` x `nodes` Chebyshev-Gauss points; with
+    pair_u the smoothed Coulomb pair potential pair_u / sqrt(r^2 + 1)."""
     v = harmonic(0.5) if potential == "harmonic" else double_well()
-    return Workload(f"box-sem-{nx}x{cells * nodes}-{potential}", nx, cells * nodes,
+    tag = "" if pair_u is None else f"-pair{pair_u:g}"
+    return Workload(f"box-sem-{nx}x{cells * nodes}-{potential}{tag}", nx, cells * nodes,
                     periodic=False, cells=cells, x_min=-15.0, x_max=15.0,
-                    k_max=10.0 * math.pi / 3.0, dt=0.01, steps=1000, vext=v, v12=None)
+                    k_max=10.0 * math.pi / 3.0, dt=0.01, steps=1000, vext=v,
+                    v12=None if pair_u is None else smoothed_coulomb(pair_u, 1.0),
+                    extra={} if pair_u is None else {"U": pair_u})
 
 
 def ensemble(seed0: int = 1000, count: int = 64):

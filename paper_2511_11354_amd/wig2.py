@@ -48,7 +48,7 @@ class TrainCfg(ctypes.Structure):
                 ("max_points", ctypes.c_int32)]
 
 PROF_NAMES = ("advect_x1", "advect_x2", "theta_stage1", "theta_stage2", "meanfield", "theta_heun",
-              "advect_x1x1")
+              "advect_x1x1", "pair_sem")
 
 FN1 = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_double, ctypes.c_void_p)
 _dp = ctypes.POINTER(ctypes.c_double)
