@@ -433,11 +433,14 @@ def main():
                     help="default: fp64 for the single-grid workloads, fp32 for the ensemble")
     ap.add_argument("--scheme", default="strang", choices=["strang", "lawson"])
     ap.add_argument("--workload", default="large",
-                    choices=["large", "tiny", "ensemble", "box", "box-pair", "surrogate", "accuracy"],
+                    choices=["large", "tiny", "ensemble", "box", "box-pair", "landau", "two-stream",
+                             "surrogate", "accuracy"],
                     help="large: periodic 128^4 (default); tiny: periodic 32^4; ensemble: 64 "
                          "uneven periodic instances; box: 129^2 x 256^2 SEM box; box-pair: the "
                          "same box with the smoothed Coulomb pair potential (two-body SEM "
-                         "operator), FP64 by default; surrogate: "
+                         "operator), FP64 by default; landau, two-stream: the Wigner-Poisson "
+                         "workloads of Sec. 5 at 256^2 x 128^2 (neutralised Poisson Hartree, "
+                         "pair potential 1/sqrt(r^2 + 1)), FP64; surrogate: "
                          "128^4 FP32 with the learned pair increment; accuracy: FP32 and "
                          "split-BF16 against FP64 at 128^4 over --steps steps")
     ap.add_argument("--potential", default="harmonic", choices=["harmonic", "double_well"],
@@ -476,6 +479,8 @@ def main():
     a.precision = a.precision or ("fp32" if a.workload == "box" else "fp64")
     if box:
         w = I.box_sem(129, 16, 16, a.potential, pair_u=1.0 if a.workload == "box-pair" else None)
+    elif a.workload in ("landau", "two-stream"):
+        w = I.plasma(a.workload, 256, 128)
     else:
         w = I.large_periodic(u=1.0) if a.workload == "large" else I.tiny_periodic()
     probe = make_solver(w, box, a.scheme, "fp64")
@@ -483,6 +488,8 @@ def main():
     probe.close()
     if a.workload == "large":
         f0 = I.mixture(x, p, seed=0, period=w.x_max - w.x_min)
+    elif a.workload in ("landau", "two-stream"):
+        f0 = I.plasma_state(x, p, w.extra["kind"], w.extra["eps"], w.extra["k"])
     elif box:
         f0 = I.symmetrised_pair(x, p, a=(-2.0, 2.0), q=(0.0, 0.0))
     else:
@@ -542,6 +549,11 @@ def make_solver(w, box, scheme, precision, lam=0.0):
     if box:
         return wig2.Solver(w.nx, w.nk, periodic=False, sem_cells=w.cells, x_min=w.x_min,
                            x_max=w.x_max, k_max=w.k_max, dt=w.dt, scheme=scheme, precision=precision)
+    if "hartree" in w.extra:  # the plasma workloads: their own mean field
+        s = wig2.Solver(w.nx, w.nk, x_min=w.x_min, x_max=w.x_max, dt=w.dt, scheme=scheme,
+                        precision=precision, meanfield_lambda=w.extra["lam"])
+        s.set_hartree(w.extra["hartree"])
+        return s
     return wig2.Solver(w.nx, w.nk, x_min=w.x_min, x_max=w.x_max, dt=w.dt, scheme=scheme,
                        precision=precision, meanfield_lambda=lam)
 
@@ -609,7 +621,7 @@ def run_form(w, f0, box, scheme, precision, steps, warmup, lam=0.0, keep_state=F
         del src, dst
     npts = w.points
     elem = 8 if precision == "fp64" else 4
-    dense_band = w.nk - 1 if lam != 0.0 else band
+    dense_band = w.nk - 1 if (lam != 0.0 or "hartree" in w.extra) else band
     pair = box and w.v12 is not None
     kernels = {}
     for name, (ms, cnt) in prof.items():

@@ -165,6 +165,21 @@ int wig2_bind_state(wig2_ctx* ctx, void* f_dev, int32_t dtype);
  * f+ = a + (dt/2) Theta[a + dt b] + (dt/2) b. */
 int wig2_step(wig2_ctx* ctx, int64_t nsteps);
 
+/* Hartree term of the mean field (meanfield_lambda != 0): V_eff gains
+ * lambda V_H[n_j] with
+ *   WIG2_HARTREE_PAIR     V_H(x_i) = dx sum_j V12(x_i - x_j) n_j(x_j), the
+ *                         pair potential of wig2_set_potentials (Sec. 2.3;
+ *                         the default);
+ *   WIG2_HARTREE_POISSON  the neutralised 1-D Coulomb potential of a uniform
+ *                         background (Sec. 3.1.1 example, the Wigner-Poisson
+ *                         system): -V_H'' = n_j - mean(n_j) on the torus,
+ *                         V_H = sum_{0<|m|<nx/2} (L/(2 pi m))^2 a_m e_m(x)
+ *                         from the density's Fourier modes a_m.
+ * Torus only for POISSON (WIG2_ENOTSUP on a box); WIG2_EINVAL for another
+ * form.  May be called before or after wig2_set_potentials; synchronises. */
+enum { WIG2_HARTREE_PAIR = 0, WIG2_HARTREE_POISSON = 1 };
+int wig2_set_hartree(wig2_ctx* ctx, int32_t form);
+
 /* Strang only: enable (default) or disable the joint launch of consecutive
  * x1 half-sweeps within a wig2_step call (results are bitwise the same; for
  * verification and timing).  0 on success. */

@@ -8,6 +8,7 @@ FFT); this module only marshals numpy arrays through ctypes.
 
 Functions follow the paper's sections:
   * grid and momentum nodes ............ Sec. 3.1 (torus), Sec. 3.2 (box, SEM)
+  * neutralised Poisson Hartree ........ Sec. 3.1.1 (1-D Coulomb example)
   * symbols sig_m, Vhat_m .............. Sec. 3.1.1 / 3.1.2 (eqs. Hartree_FSM,
                                          two_body_FSM; sign: eq. sWigner)
   * SEM single-body matrix ............. Sec. 3.2.1 (eq. Chebyshev_PDO)
@@ -40,7 +41,7 @@ class Grid(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("scheme", ctypes.c_int), ("lam", ctypes.c_double),
                 ("xc", ctypes.c_int), ("xc_n0", ctypes.c_double), ("n_scale", ctypes.c_double),
-                ("two_body", ctypes.c_int)]
+                ("two_body", ctypes.c_int), ("hartree", ctypes.c_int)]
 
 
 class Tables(ctypes.Structure):
@@ -77,6 +78,7 @@ def lib():
             "or_sigma_hxc": ([G, _dp, _dp], None),
             "or_veff_hxc": ([G, P, _dp, _dp, _dp], None),
             "or_densities": ([G, _dp, _dp, _dp], None),
+            "or_hartree_poisson": ([G, _dp, _dp], None),
             "or_theta_periodic": ([G, _dp, _dp, _dp, ctypes.c_int, ctypes.c_long, ctypes.c_long,
                                    _dp, _dp], None),
             "or_theta_dense": ([G, _dp, _dp, ctypes.c_long, ctypes.c_long, _dp, _dp], None),
@@ -181,10 +183,21 @@ def densities(g: Grid, f: np.ndarray):
     return n1, n2
 
 
-def veff_hxc(g: Grid, lam, xc, xc_n0, n_scale, v12_pair, n):
-    prm = Params(0.0, 0, lam, int(xc), xc_n0, n_scale, 1)
+def veff_hxc(g: Grid, lam, xc, xc_n0, n_scale, v12_pair, n, hartree="pair"):
+    prm = Params(0.0, 0, lam, int(xc), xc_n0, n_scale, 1, HARTREE[hartree])
     v = np.zeros(g.nx)
-    lib().or_veff_hxc(ctypes.byref(g), ctypes.byref(prm), _p(v12_pair), _p(n), _p(v))
+    lib().or_veff_hxc(ctypes.byref(g), ctypes.byref(prm), _p(v12_pair), _p(np.ascontiguousarray(n, dtype=np.float64)),
+                      _p(v))
+    return v
+
+
+HARTREE = {"pair": 0, "poisson": 1}
+
+
+def hartree_poisson(g: Grid, n):
+    """Neutralised-background Poisson Hartree potential (Sec. 3.1.1 example)."""
+    v = np.zeros(g.nx)
+    lib().or_hartree_poisson(ctypes.byref(g), _p(np.ascontiguousarray(n, dtype=np.float64)), _p(v))
     return v
 
 
@@ -278,9 +291,10 @@ def tables(g: Grid, vext=None, v12=None):
 
 def step(g: Grid, f: np.ndarray, tb: dict, nsteps: int, dt: float, scheme: str = "strang",
          lam: float = 0.0, xc: bool = False, xc_n0: float = 1.0, n_scale: float = 1.0,
-         two_body: bool = True) -> np.ndarray:
+         two_body: bool = True, hartree: str = "pair") -> np.ndarray:
     out = np.ascontiguousarray(f, dtype=np.float64).copy()
-    prm = Params(dt, 0 if scheme == "strang" else 1, lam, int(xc), xc_n0, n_scale, int(two_body))
+    prm = Params(dt, 0 if scheme == "strang" else 1, lam, int(xc), xc_n0, n_scale, int(two_body),
+                 HARTREE[hartree])
     t = Tables(_p(tb["sig_ext"]), _p(tb["vhat12"]), _p(tb["K"]), _p(tb["v12_pair"]), _p(tb.get("v12_sem")))
     rc = lib().or_step(ctypes.byref(g), ctypes.byref(prm), ctypes.byref(t), _p(out), nsteps)
     if rc:

@@ -214,11 +214,46 @@ void or_veff_hxc(const or_grid* g, const or_params* prm, const double* v12_pair,
 {
     int nx = g->nx;
     double dx = or_dx(g);
+    double* vh = NULL;
+    if (prm->hartree == 1) {
+        vh = malloc(sizeof(double) * nx);
+        or_hartree_poisson(g, n, vh);
+    }
     for (int i = 0; i < nx; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < nx; ++j) s += v12_pair[(long)i * nx + j] * n[j];
-        v[i] = prm->lambda * dx * s;
+        if (vh) {
+            v[i] = prm->lambda * vh[i];
+        } else {
+            double s = 0.0;
+            for (int j = 0; j < nx; ++j) s += v12_pair[(long)i * nx + j] * n[j];
+            v[i] = prm->lambda * dx * s;
+        }
         if (prm->xc) v[i] += or_hl(prm->n_scale * n[i]) - or_hl(prm->xc_n0);
+    }
+    free(vh);
+}
+
+/* Hartree potential of the neutralised 1-D Coulomb system on the torus
+ * (Sec. 3.1.1, example of the neutralised ion background): with the Fourier
+ * coefficients a_m = (1/nx) sum_j n(x_j) e^{2 pi i m x_j / L} of the density,
+ * whose zero mode the background cancels,
+ *   V_H(x_i) = sum_{0 < |m| < nx/2} (L^2 / (4 pi^2 m^2)) a_m e^{-2 pi i m x_i / L},
+ * the solution of -V_H'' = n - mean(n) (the Nyquist mode is dropped, as for
+ * the other density-driven symbols). */
+void or_hartree_poisson(const or_grid* g, const double* n, double* v)
+{
+    int nx = g->nx;
+    double L = or_len(g), dx = or_dx(g);
+    for (int i = 0; i < nx; ++i) {
+        double complex acc = 0.0;
+        double xi = g->x_min + i * dx;
+        for (int m = -(nx - 1) / 2; m <= (nx - 1) / 2; ++m) {
+            if (m == 0 || 2 * abs(m) >= nx) continue;
+            double complex am = 0.0;
+            for (int j = 0; j < nx; ++j) am += n[j] * cexp(2.0 * I * OR_PI * m * (g->x_min + j * dx) / L);
+            am /= nx;
+            acc += L * L / (4.0 * OR_PI * OR_PI * m * m) * am * cexp(-2.0 * I * OR_PI * m * xi / L);
+        }
+        v[i] = creal(acc);
     }
 }
 

@@ -33,6 +33,8 @@ typedef struct {
     int xc;            /* 1: add the Hedin-Lundqvist exchange-correlation term   */
     double xc_n0, n_scale;
     int two_body;      /* 1: include Theta_V12                                   */
+    int hartree;       /* 0: Hartree by convolution with V12 (Sec. 2.3); 1: the
+                          neutralised Poisson potential (Sec. 3.1.1 example)   */
 } or_params;
 
 typedef struct {
@@ -56,6 +58,7 @@ void or_sigma_hxc(const or_grid* g, const double* v_x, double* sig);
 void or_veff_hxc(const or_grid* g, const or_params* prm, const double* v12_pair,
                  const double* n, double* v);
 void or_densities(const or_grid* g, const double* f, double* n1, double* n2);
+void or_hartree_poisson(const or_grid* g, const double* n, double* v);
 
 void or_theta_periodic(const or_grid* g, const double* sig1, const double* sig2,
                        const double* vhat12, int two_body,

@@ -66,6 +66,8 @@ struct wig2_ctx {
     double *p_d = nullptr, *w_d = nullptr, *thomas_d = nullptr;
     double *sig_ext_d = nullptr, *sig1_d = nullptr, *sig2_d = nullptr, *kap_d = nullptr;
     double *ksem_d = nullptr, *v12pair_d = nullptr, *sintab_d = nullptr;
+    int hartree = WIG2_HARTREE_PAIR;
+    double* hart_d = nullptr;  // [nx][nx] Hartree kernel of the mean field
     float* ksem_f = nullptr;  // FP32 copy of the SEM matrices (nk = 256, FP32 / BF16X2)
     // box with a pair potential: the two-body SEM operator's tables (element
     // type of the state), its per-chunk workspaces and a state-sized
@@ -239,7 +241,7 @@ MeanFieldArgs mf_args(wig2_ctx* c)
     a.xc = c->prm.xc;
     a.xc_n0 = c->prm.xc_n0;
     a.n_scale = c->prm.n_scale;
-    a.v12pair = c->v12pair_d;
+    a.v12pair = c->hart_d;
     a.sig_ext = c->sig_ext_d;
     a.sintab = c->sintab_d;
     a.dens = c->mf_dens_d;
@@ -918,7 +920,8 @@ int wig2_create(const wig2_grid* grid, const wig2_params* prm, void* hip_stream,
     if (dev_alloc(c, &c->p_d, nk) || dev_alloc(c, &c->w_d, nk) || dev_alloc(c, &c->thomas_d, nx) ||
         dev_alloc(c, &c->sig_ext_d, (size_t)nx * nk) || dev_alloc(c, &c->sig1_d, (size_t)nx * nk) ||
         dev_alloc(c, &c->sig2_d, (size_t)nx * nk) || dev_alloc(c, &c->kap_d, (size_t)nx * nk) ||
-        dev_alloc(c, &c->v12pair_d, np) || dev_alloc(c, &c->sintab_d, (size_t)nk * nx) ||
+        dev_alloc(c, &c->v12pair_d, np) || dev_alloc(c, &c->hart_d, np) ||
+        dev_alloc(c, &c->sintab_d, (size_t)nk * nx) ||
         dev_alloc(c, &c->mf_dens_d, 2 * (size_t)nx) || dev_alloc(c, &c->mf_veff_d, 2 * (size_t)nx) ||
         dev_alloc(c, &c->s0_d, np) || dev_alloc(c, &c->s0b_d, np) || dev_alloc(c, &c->skin_d, np) ||
         dev_alloc(c, &c->s2_d, np) || dev_alloc(c, &c->rows_d, np * nk) ||
@@ -955,7 +958,7 @@ void wig2_destroy(wig2_ctx* c)
     if (!c) return;
     if (c->st) hipStreamSynchronize(c->st);
     void* bufs[] = {c->f_own, c->k1, c->tmp, c->work, c->p_d, c->w_d, c->thomas_d, c->sig_ext_d, c->sig1_d,
-                    c->sig2_d, c->kap_d, c->ksem_d, c->ksem_f, c->v12pair_d, c->sintab_d,
+                    c->sig2_d, c->kap_d, c->ksem_d, c->ksem_f, c->v12pair_d, c->hart_d, c->sintab_d,
                     c->mf_dens_d, c->mf_veff_d, c->s0_d, c->s0b_d, c->skin_d, c->s2_d, c->rows_d,
                     c->f1_d, c->ft, c->fs, c->sur_buf, c->s12_wa, c->s12_wb, c->s12_wc, c->s12_wd,
                     c->s12_dt, c->s12_wr, c->s12_wh, c->s12_acc};
@@ -1006,6 +1009,27 @@ int upload_sem12(wig2_ctx* c, const Sem12Tables& t)
             return fail(c, WIG2_ENOMEM, "two-body SEM workspaces");
     }
     return WIG2_OK;
+}
+
+// Kernel of the mean field's Hartree term, V_H(x_i) = dx sum_j K[i][j] n(x_j):
+// the pair potential K[i][j] = V12(x_i - x_j) (Sec. 2.3), or the neutralised
+// 1-D Poisson potential (Sec. 3.1.1 example), -V_H'' = n - mean(n) on the
+// torus, whose modes are V_m = (L / (2 pi m))^2 a_m for 0 < |m| < nx/2:
+// K[i][j] = (1 / (nx dx)) sum_{0 < |m| < nx/2} (L / (2 pi m))^2 cos(2 pi m (i - j) / nx).
+int upload_hartree(wig2_ctx* c)
+{
+    const int nx = c->g.nx;
+    if (c->hartree == WIG2_HARTREE_PAIR) return upload(c, c->hart_d, c->v12pair) ? WIG2_EDEVICE : WIG2_OK;
+    const double L = c->g.L(), pi = 3.141592653589793238462643383279502884;
+    std::vector<double> row(nx, 0.0), K((size_t)nx * nx);
+    for (int d = 0; d < nx; ++d)
+        for (int m = 1; 2 * m < nx; ++m) {
+            const double a = L / (2.0 * pi * m);
+            row[d] += 2.0 * a * a * std::cos(2.0 * pi * m * d / nx);
+        }
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < nx; ++j) K[(size_t)i * nx + j] = row[(i - j + nx) % nx] / (nx * c->g.dx());
+    return upload(c, c->hart_d, K) ? WIG2_EDEVICE : WIG2_OK;
 }
 
 int wig2_set_potentials(wig2_ctx* c, wig2_fn1 v_ext, wig2_fn1 v12, void* user)
@@ -1083,6 +1107,7 @@ int wig2_set_potentials(wig2_ctx* c, wig2_fn1 v_ext, wig2_fn1 v12, void* user)
         }
     }
     if (upload(c, c->v12pair_d, c->v12pair)) return WIG2_EDEVICE;
+    if (int rc = upload_hartree(c)) return rc;
     c->has_pot = true;
     c->err.clear();
     return WIG2_OK;
@@ -1245,6 +1270,17 @@ int wig2_advect_noalloc(wig2_ctx* c, int32_t dim, double s, const void* in, void
                        : launch_advect<float>((const float*)in, (float*)out, (float*)ws, c->g.nx, c->g.nk,
                                               dim, c->g.periodic != 0, cpp, maxc, c->p_d, c->thomas_d, c->st);
     if (e != hipSuccess) return fail(c, WIG2_EDEVICE, "advect_noalloc: launch failed");
+    return WIG2_OK;
+}
+
+int wig2_set_hartree(wig2_ctx* c, int32_t form)
+{
+    if (!c || (form != WIG2_HARTREE_PAIR && form != WIG2_HARTREE_POISSON)) return WIG2_EINVAL;
+    if (form == WIG2_HARTREE_POISSON && !c->g.periodic)
+        return fail(c, WIG2_ENOTSUP, "the neutralised Poisson Hartree term needs a torus");
+    HIPCHK(c, hipStreamSynchronize(c->st));  // queued steps read the current kernel
+    c->hartree = form;
+    if (c->has_pot) return upload_hartree(c);
     return WIG2_OK;
 }
 

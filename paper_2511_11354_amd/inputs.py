@@ -211,3 +211,41 @@ def ensemble(seed0: int = 1000, count: int = 64):
         out.append(Workload(f"ens-{s}", nx, nk, dt=0.005, steps=1000, vext=cosine(0.5, 20.0),
                             v12=smoothed_coulomb(u, 1.0), extra={"U": u, "seed": seed0 + s}))
     return out
+
+
+# --------------------------------------------------------------------------
+# Plasma workloads of Sec. 5 (Wigner-Poisson with the two-body term)
+# --------------------------------------------------------------------------
+
+
+def plasma_state(x, p, kind="landau", eps=0.1, k=0.4, dtype=np.float64):
+    """Uncorrelated initial states of Sec. 5, f(x1,x2,p1,p2) = g(x1,p1) g(x2,p2):
+      landau:     g = (1/sqrt(2 pi)) (1 + eps cos k x) e^{-p^2/2}
+      two-stream: g = (1 + eps cos k x) (1 + 5 p^2) e^{-p^2/2} / (6 sqrt(2 pi))
+    (the printed 1/(2 pi) and 1/(6 sqrt(2 pi))^2 split between the particles)."""
+    X, P = np.meshgrid(np.asarray(x, float), np.asarray(p, float), indexing="ij")
+    if kind == "landau":
+        g = (1 + eps * np.cos(k * X)) * np.exp(-P**2 / 2) / math.sqrt(2 * math.pi)
+    elif kind == "two-stream":
+        g = (1 + eps * np.cos(k * X)) * (1 + 5 * P**2) * np.exp(-P**2 / 2) / (6 * math.sqrt(2 * math.pi))
+    else:
+        raise ValueError(kind)
+    return np.ascontiguousarray(np.einsum("ac,bd->abcd", g, g).astype(dtype))
+
+
+def plasma(kind="landau", nx=256, nk=128, eps=None, pair_eps=1.0, gamma=1.0, two_body=True) -> Workload:
+    """Quantum Landau damping / two-stream instability of Sec. 5: torus
+    [-5 pi, 5 pi] (dx = 5 pi / 128 at nx = 256; the printed 257 nodes count
+    the periodic end twice), dp = hbar pi / L = 0.1 (nk = 128: p in
+    [-6.4, 6.3]), dt = 0.01, no V_ext; the neutralised-Poisson Hartree term
+    with weight 1/L (reading: the density in the Poisson equation per unit
+    length of the other particle's coordinate, so the plasma frequency is 1),
+    and the pair potential gamma / sqrt(r^2 + pair_eps) when two_body."""
+    L = 10 * math.pi
+    if eps is None:
+        eps = 0.1 if kind == "landau" else 0.02
+    v12 = smoothed_coulomb(gamma, pair_eps) if two_body else None
+    tag = f"-pair{pair_eps:g}" if two_body else "-hartree"
+    return Workload(f"{kind}-{nx}x{nk}{tag}", nx, nk, x_min=-L / 2, x_max=L / 2, dt=0.01, steps=20000,
+                    vext=None, v12=v12,
+                    extra={"kind": kind, "eps": eps, "k": 0.4, "lam": 1.0 / L, "hartree": "poisson"})

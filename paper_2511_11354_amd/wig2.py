@@ -74,6 +74,7 @@ SIGNATURES = {
     "wig2_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32], ctypes.c_int),
     "wig2_band": ([_vp], ctypes.c_int),
     "wig2_set_theta_path": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "wig2_set_hartree": ([_vp, ctypes.c_int32], ctypes.c_int),
     "wig2_set_sweep_fusion": ([_vp, ctypes.c_int32], ctypes.c_int),
     "wig2_theta_path": ([_vp], ctypes.c_int),
     "wig2_batch_create": ([ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params), _vp,
@@ -266,6 +267,13 @@ class Solver:
         self._check(self._L.wig2_profile_read(self._h, _ptr(ms), cnt, int(reset)),
                     "wig2_profile_read")
         return {n: (float(ms[i]), int(cnt[i])) for i, n in enumerate(PROF_NAMES)}
+
+    HARTREE = {"pair": 0, "poisson": 1}
+
+    def set_hartree(self, form: str):
+        """Hartree term of the mean field: "pair" (convolution with V12) or
+        "poisson" (neutralised 1-D Coulomb, the Wigner-Poisson system)."""
+        self._check(self._L.wig2_set_hartree(self._h, self.HARTREE[form]), "wig2_set_hartree")
 
     def set_sweep_fusion(self, enable=True):
         """Strang: run consecutive x1 half-sweeps of a multi-step call as one

@@ -456,6 +456,69 @@ def test_meanfield_chain_closed_form(orc):
     assert worst <= 1e-15
 
 
+@pytest.mark.parametrize("nx", [64, 65])
+def test_hartree_poisson_closed_form(orc, nx):
+    """Neutralised 1-D Coulomb Hartree term (Sec. 3.1.1 example): for
+    n = c + sum_k (a_k cos + b_k sin)(2 pi k x / L) the solution of
+    -V'' = n - mean(n) is sum_k (L/(2 pi k))^2 (a_k cos + b_k sin); modes at or
+    above nx/2 are not resolved (the Nyquist mode is dropped)."""
+    L = 10 * np.pi
+    g = orc.grid(nx, 32, True, 1, -L / 2, L / 2)
+    x = orc.xnodes(g)
+    modes = [(1, 0.3, -0.2), (2, 0.05, 0.4), (5, -0.1, 0.07), (11, 0.02, 0.0)]
+    n = 3.0 + sum(a * np.cos(2 * np.pi * k * x / L) + b * np.sin(2 * np.pi * k * x / L) for k, a, b in modes)
+    ex = sum((L / (2 * np.pi * k)) ** 2 * (a * np.cos(2 * np.pi * k * x / L) + b * np.sin(2 * np.pi * k * x / L))
+             for k, a, b in modes)
+    v = orc.hartree_poisson(g, n)
+    assert np.abs(v - ex).max() <= 1e-12 * np.abs(ex).max()
+    if nx % 2 == 0:
+        nyq = np.cos(np.pi * np.arange(nx))
+        assert np.abs(orc.hartree_poisson(g, nyq)).max() <= 1e-12
+    assert np.abs(orc.veff_hxc(g, 0.5, False, 1.0, 1.0, np.zeros((nx, nx)), n, hartree="poisson") - 0.5 * ex).max() \
+        <= 1e-12 * np.abs(ex).max()
+
+
+def test_poisson_meanfield_chain_cosine(orc):
+    """The Wigner-Poisson chain of the Landau-damping workload (Sec. 5) on its
+    initial state f = (1/2 pi)(1 + eps cos k x1)(1 + eps cos k x2)
+    e^{-(p1^2 + p2^2)/2} (k = 0.4, L = 10 pi): n1 = L (1 + eps cos k x), so
+    V_H = (L eps / k^2) cos k x, and a single cosine mode A cos k x acts as
+    the exact shift Theta_1 f = (A/hbar) sin(k x1) [f(p1 - hbar k/2) -
+    f(p1 + hbar k/2)] (hbar k / 2 = 2 dp here), f = 0 off the p-box."""
+    L, k, eps = 10 * np.pi, 0.4, 0.05
+    g = orc.grid(16, 128, True, 1, -L / 2, L / 2)  # the workload's p-box [-6.4, 6.3]
+    x = orc.xnodes(g)
+    p, _ = orc.pnodes(g)
+    X1, X2, P1, P2 = _mesh(x, p)
+    prof = lambda X: 1 + eps * np.cos(k * X)
+    f = np.ascontiguousarray(prof(X1) * prof(X2) * np.exp(-(P1**2 + P2**2) / 2) / (2 * np.pi))
+    n1, n2 = orc.densities(g, f)
+    vh = orc.veff_hxc(g, 1.0, False, 1.0, 1.0, np.zeros((g.nx, g.nx)), n1, hartree="poisson")
+    A = L * eps / k**2
+    assert np.abs(vh - A * np.cos(k * x)).max() <= 1e-9 * A
+    sig = orc.sigma_hxc(g, vh)
+    th = orc.theta_periodic(g, sig, sig, np.zeros(g.nk), f, two_body=False)
+    m0 = int(round(k / 2 / (np.pi / L)))
+    assert m0 == 2
+
+    def shifted(F, s, axis):
+        out = np.zeros_like(F)
+        n = F.shape[axis]
+        src = [slice(None)] * 4
+        dst = [slice(None)] * 4
+        if s > 0:
+            src[axis], dst[axis] = slice(0, n - s), slice(s, n)
+        else:
+            src[axis], dst[axis] = slice(-s, n), slice(0, n + s)
+        out[tuple(dst)] = F[tuple(src)]
+        return out   # out[n] = F[n - s], zero off the box
+
+    ex = (A * np.sin(k * X1) * (shifted(f, m0, 2) - shifted(f, -m0, 2))
+          + A * np.sin(k * X2) * (shifted(f, m0, 3) - shifted(f, -m0, 3)))
+    assert np.abs(ex).max() > 1e-3
+    assert np.abs(th - ex).max() <= 1e-9 * np.abs(ex).max()
+
+
 def test_dense_theta_orientation_harmonic(orc):
     """or_theta_dense with the SEM matrix of V = omega^2 x^2 / 2 on both
     particles (Sec. 3.2.1): for a quadratic potential the Wigner operator is
