@@ -254,6 +254,109 @@ __global__ __launch_bounds__(64) void k_advect_reg(const T* __restrict__ in, T* 
 }
 
 // ---------------------------------------------------------------------------
+// Segmented periodic line (NX = NSEG x 32, displacement of at most one cell):
+// a workgroup of NSEG waves takes 64 lines, wave s holding segment s (32
+// points) of each line in registers, so loads and stores stay one
+// contiguous run per wave as in the register-resident sweep.  Each recursive
+// filter runs inside the segment from a zero start and is completed with the
+// neighbour segment's zero-start end value: the causal value entering
+// segment s, sum_{k>=0} z1^k g[start - 1 - k], equals the previous segment's
+// zero-start end value up to z1^32 (5e-19) of its size, and likewise for the
+// anti-causal filter, so the result is the periodic solve's.  The FIR window
+// (two points on each side) takes the neighbours' edge coefficients through
+// LDS.  PASSES = 2 applies the sweep twice, as the register-resident kernel.
+// ---------------------------------------------------------------------------
+template <typename T, int NX, int PASSES>
+__global__ __launch_bounds__(NX / 32 * 64) void k_advect_seg(const T* __restrict__ in, T* __restrict__ out,
+                                                           int nk, int dim, long nlines, double cpp,
+                                                           const double* __restrict__ pn)
+{
+    constexpr int S = 32, NSEG = NX / S;
+    static_assert(NX % S == 0 && NSEG >= 2, "segments of 32 points");
+    __shared__ double ends[2][NSEG][64];  // zero-start filter values at the segment ends
+    __shared__ T edge[4][NSEG][64];       // first two and last two coefficients
+    const int lane = threadIdx.x & 63, sg = threadIdx.x >> 6;
+    const int prv = (sg + NSEG - 1) % NSEG, nxt = (sg + 1) % NSEG;
+    const long line = (long)blockIdx.x * 64 + lane;
+    const bool act = line < nlines;
+    const LineMap lm = line_map(act ? line : 0, NX, nk, dim);
+    double c = cpp * pn[lm.nv];
+    asm volatile("" : "+v"(c));
+    const Taps tp = line_taps<T, true>(c);
+    double ad[5];
+#pragma unroll
+    for (int d = -2; d <= 2; ++d) {
+        const int k = d - tp.J + 1;
+        ad[d + 2] = (k == 0) ? tp.a[0] : (k == 1) ? tp.a[1] : (k == 2) ? tp.a[2] : (k == 3) ? tp.a[3] : 0.0;
+    }
+    constexpr T z1 = spline_pole<T>();
+    constexpr double z1d = (double)z1;
+    const long b0 = lm.base + (long)sg * S * lm.stride;
+    T v[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) v[i] = act ? __builtin_nontemporal_load(&in[b0 + (long)i * lm.stride]) : T(0);
+
+#pragma unroll
+    for (int pass = 0; pass < PASSES; ++pass) {
+        // causal filter: zero start, then the entering value from segment s-1
+#pragma unroll
+        for (int i = 1; i < S; ++i) v[i] += z1 * v[i - 1];
+        ends[0][sg][lane] = (double)v[S - 1];
+        __syncthreads();
+        {
+            const double t = ends[0][prv][lane];
+            double zp = z1d;
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                v[i] = T((double)v[i] + zp * t);
+                zp *= z1d;
+            }
+        }
+        // anti-causal filter: zero start at the segment end, then the value
+        // entering from segment s+1
+#pragma unroll
+        for (int i = S - 2; i >= 0; --i) v[i] += z1 * v[i + 1];
+        ends[1][sg][lane] = (double)v[0];
+        __syncthreads();
+        {
+            const double h = ends[1][nxt][lane];
+            double zp = z1d;
+#pragma unroll
+            for (int i = S - 1; i >= 0; --i) {
+                v[i] = T((double)v[i] + zp * h);
+                zp *= z1d;
+            }
+        }
+        edge[0][sg][lane] = v[0];
+        edge[1][sg][lane] = v[1];
+        edge[2][sg][lane] = v[S - 2];
+        edge[3][sg][lane] = v[S - 1];
+        __syncthreads();
+        const T em2 = edge[2][prv][lane], em1 = edge[3][prv][lane];
+        const T ep0 = edge[0][nxt][lane], ep1 = edge[1][nxt][lane];
+        auto eta = [&](int j) -> T { return j == -2 ? em2 : j == -1 ? em1 : j == S ? ep0 : j == S + 1 ? ep1 : v[j]; };
+        T r[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            double acc = 0.0;
+#pragma unroll
+            for (int d = -2; d <= 2; ++d) acc += ad[d + 2] * (double)eta(i + d);
+            r[i] = T(acc);
+        }
+        if (pass + 1 < PASSES) {
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                v[i] = r[i];
+                asm volatile("" : "+v"(v[i]));
+            }
+        } else if (act) {
+#pragma unroll
+            for (int i = 0; i < S; ++i) __builtin_nontemporal_store(r[i], &out[b0 + (long)i * lm.stride]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // General line (any nx, any displacement): the coefficients go through a
 // state-sized scratch array laid out like the state (coalesced).
 // ---------------------------------------------------------------------------
@@ -406,7 +509,7 @@ template hipError_t launch_advect_batch<float>(const float*, float*, const Batch
 bool advect_in_registers(int nx, bool periodic, double max_cells)
 {
     if (!(max_cells <= 1.0)) return false;
-    if (periodic) return nx == 16 || nx == 32 || nx == 48 || nx == 64 || nx == 96 || nx == 128;
+    if (periodic) return nx == 16 || nx == 32 || nx == 48 || nx == 64 || nx == 96 || nx == 128 || nx == 256;
     return nx == 33 || nx == 65 || nx == 129;
 }
 
@@ -428,6 +531,16 @@ hipError_t launch_advect(const T* in, T* out, T* work, int nx, int nk, int dim, 
             case 64: return run_reg<T, 64, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
             case 96: return run_reg<T, 96, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
             case 128: return run_reg<T, 128, true>(in, out, nk, dim, nl, cpp, p_dev, thomas_dev, passes, st);
+            case 256: {
+                const unsigned nb = (unsigned)((nl + 63) / 64);
+                if (passes == 2)
+                    hipLaunchKernelGGL((k_advect_seg<T, 256, 2>), dim3(nb), dim3(512), 0, st, in, out, nk, dim, nl,
+                                       cpp, p_dev);
+                else
+                    hipLaunchKernelGGL((k_advect_seg<T, 256, 1>), dim3(nb), dim3(512), 0, st, in, out, nk, dim, nl,
+                                       cpp, p_dev);
+                return hipGetLastError();
+            }
             default: break;
             }
         } else {

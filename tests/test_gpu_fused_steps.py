@@ -46,6 +46,9 @@ CASES = {
     # nx = 128: the register-resident sweep of 128-point lines, and the joint
     # two-pass x1 launch of the 128^4 workload
     "stream-128x32": (128, 32, True, 1, I.cosine(0.5, 20.0), I.smoothed_coulomb(1.0, 1.0), "stream"),
+    # nx = 256: segmented periodic lines (8 waves x 32 points per line), the
+    # sweep of the Wigner-Poisson workloads, with its joint x1 launch
+    "seg-256x16": (256, 16, True, 1, I.cosine(0.5, 20.0), I.smoothed_coulomb(1.0, 1.0), "auto"),
     # nx = 129 box: the natural-boundary register sweep of the box workload
     "box-129": (129, 32, False, 4, I.harmonic(0.5), None, "auto"),
 }
@@ -114,7 +117,7 @@ def test_multi_step_matches_oracle(orc, case):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("case", ["stream-32x128", "stream-128x32", "box-129"])
+@pytest.mark.parametrize("case", ["stream-32x128", "stream-128x32", "box-129", "seg-256x16"])
 def test_multi_step_fp32_matches_oracle(orc, case):
     """The FP32 form of the same launch configurations, 3 steps in one call,
     against the FP64 oracle at the FP32 bound (state rounding ~6e-8 per step

@@ -115,6 +115,7 @@ def test_theta_reduced_precision(orc, precision, tol):
 @pytest.mark.parametrize("nx,nk,periodic,s", [
     (32, 16, True, 0.01), (48, 16, True, -0.02), (24, 16, True, 0.01),   # 24: general path
     (16, 32, True, 3.0),                                                 # > 1 cell: general path
+    (256, 16, True, 0.01), (256, 16, True, -0.05),                       # 256: segmented lines
     (33, 16, False, 0.01), (20, 16, False, 0.05), (33, 16, False, 2.5),
 ])
 @pytest.mark.parametrize("dim", [1, 2])
@@ -133,12 +134,13 @@ def test_advect_fp64_matches_oracle(orc, nx, nk, periodic, s, dim):
     assert e <= 1e-12
 
 
-def test_advect_fp32(orc):
-    sol, g = make(orc, 32, 32, precision="fp32")
-    f = I.random_field((32, 32, 32, 32), seed=5)
-    ref = orc.advect(g, 2, 0.02, f)
+@pytest.mark.parametrize("nx,nk,dim", [(32, 32, 2), (256, 16, 1), (256, 16, 2)])
+def test_advect_fp32(orc, nx, nk, dim):
+    sol, g = make(orc, nx, nk, precision="fp32")
+    f = I.random_field((nx, nx, nk, nk), seed=5)
+    ref = orc.advect(g, dim, 0.02, f)
     out = torch.empty(f.shape, dtype=torch.float32, device="cuda")
-    sol.advect(2, 0.02, dev(f, torch.float32), out)
+    sol.advect(dim, 0.02, dev(f, torch.float32), out)
     torch.cuda.synchronize()
     assert eps_inf(host(out), ref) <= 2e-6
 
