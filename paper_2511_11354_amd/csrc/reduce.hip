@@ -20,7 +20,9 @@ __device__ inline double wave_sum(double v)
 }
 
 // One workgroup (256 threads, 4 waves) per plane.  Wave w handles rows
-// n1 = w, w+4, ...; lanes stride over n2.
+// n1 = w, w+4, ...; lanes stride over n2.  With `rows` the row sums are
+// reduced per row (the reduced Wigner function needs them); without, each
+// lane keeps its weighted partial moments and the wave reduces once.
 template <typename T>
 __global__ __launch_bounds__(256) void k_plane_moments(const T* __restrict__ f, int nk,
                                                        const double* __restrict__ p,
@@ -35,7 +37,32 @@ __global__ __launch_bounds__(256) void k_plane_moments(const T* __restrict__ f, 
     const T* F = f + pl * (long)nk * nk;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double a0 = 0.0, ak = 0.0, a2 = 0.0;
-    for (int n1 = wv; n1 < nk; n1 += 4) {
+    if (!rows) {
+        // no per-row sums wanted: every moment is a weighted sum of the
+        // thread's own terms (pairs of neighbours in n2, read as one vector),
+        // reduced once per wave at the end
+        typedef T T2 __attribute__((ext_vector_type(2)));
+        const T2* F2 = reinterpret_cast<const T2*>(F);
+        const int half = nk * nk / 2;
+#pragma unroll 4
+        for (int e = threadIdx.x; e < half; e += 256) {
+            const T2 v2 = F2[e];
+            const int n1 = (2 * e) / nk, n2 = (2 * e) % nk;
+            const double w1 = w[n1], pp1 = p[n1] * p[n1];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double v = (double)v2[h];
+                const double ww = w1 * w[n2 + h] * v;
+                a0 += ww;
+                ak += ww * (pp1 + p[n2 + h] * p[n2 + h]) * inv2m;
+                a2 += ww * v;
+            }
+        }
+        a0 = wave_sum(a0);
+        ak = wave_sum(ak);
+        a2 = wave_sum(a2);
+    }
+    for (int n1 = wv; rows && n1 < nk; n1 += 4) {
         double r0 = 0.0, rp = 0.0, rq = 0.0;
         for (int n2 = lane; n2 < nk; n2 += 64) {
             const double v = (double)F[(long)n1 * nk + n2];
