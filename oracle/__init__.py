@@ -79,6 +79,7 @@ def lib():
             "or_veff_hxc": ([G, P, _dp, _dp, _dp], None),
             "or_densities": ([G, _dp, _dp, _dp], None),
             "or_hartree_poisson": ([G, _dp, _dp], None),
+            "or_hartree_padded": ([G, _dp, _dp, _dp], None),
             "or_theta_periodic": ([G, _dp, _dp, _dp, ctypes.c_int, ctypes.c_long, ctypes.c_long,
                                    _dp, _dp], None),
             "or_theta_dense": ([G, _dp, _dp, ctypes.c_long, ctypes.c_long, _dp, _dp], None),
@@ -192,6 +193,21 @@ def veff_hxc(g: Grid, lam, xc, xc_n0, n_scale, v12_pair, n, hartree="pair"):
 
 
 HARTREE = {"pair": 0, "poisson": 1}
+
+
+def hartree_padded_points(g: Grid) -> np.ndarray:
+    """Separations nu dx, nu in [-3nx/2, 3nx/2), at which the zero-padded box
+    Hartree term samples V12."""
+    nt = 3 * g.nx
+    return np.arange(-(nt // 2), nt - nt // 2) * dx(g)
+
+
+def hartree_padded(g: Grid, v12_pad, n):
+    """Box Hartree potential by the zero-padded transform (Sec. 3.2.1 remark)."""
+    v = np.zeros(g.nx)
+    lib().or_hartree_padded(ctypes.byref(g), _p(np.ascontiguousarray(v12_pad, dtype=np.float64)),
+                            _p(np.ascontiguousarray(n, dtype=np.float64)), _p(v))
+    return v
 
 
 def hartree_poisson(g: Grid, n):

@@ -257,6 +257,36 @@ void or_hartree_poisson(const or_grid* g, const double* n, double* v)
     }
 }
 
+/* Hartree potential of a box density by the zero-padded transform of
+ * Sec. 3.2.1 (remark, eq. Hartree_approximation): the density, zero outside
+ * the box, and V12 sampled at nu dx for nu in [-Nt/2, Nt/2) are transformed on
+ * the padded grid of Nt = 3 nx points, multiplied and transformed back,
+ *   V_H(x_m) = dx (1/Nt) sum_l Vt_l nt_l e^{2 pi i l m / Nt},
+ *   Vt_l = sum_nu V12(nu dx) e^{-2 pi i l nu / Nt},  nt_l = sum_j n_j e^{-2 pi i l j / Nt}.
+ * v12_pad[nu + Nt/2] = V12(nu dx). */
+void or_hartree_padded(const or_grid* g, const double* v12_pad, const double* n, double* v)
+{
+    int nx = g->nx, nt = 3 * nx;
+    double dx = or_dx(g);
+    double complex* vt = malloc(sizeof(double complex) * nt);
+    double complex* ntl = malloc(sizeof(double complex) * nt);
+    for (int l = 0; l < nt; ++l) {
+        double complex a = 0.0, b = 0.0;
+        for (int nu = -nt / 2; nu < nt - nt / 2; ++nu)
+            a += v12_pad[nu + nt / 2] * cexp(-2.0 * I * OR_PI * l * nu / nt);
+        for (int j = 0; j < nx; ++j) b += n[j] * cexp(-2.0 * I * OR_PI * l * j / nt);
+        vt[l] = a;
+        ntl[l] = b;
+    }
+    for (int m = 0; m < nx; ++m) {
+        double complex acc = 0.0;
+        for (int l = 0; l < nt; ++l) acc += vt[l] * ntl[l] * cexp(2.0 * I * OR_PI * l * m / nt);
+        v[m] = dx * creal(acc) / nt;
+    }
+    free(vt);
+    free(ntl);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Theta application                                                         */
 /* ------------------------------------------------------------------------ */
@@ -770,6 +800,7 @@ typedef struct {
     const or_tables* tb;
     double *sig1, *sig2;  /* periodic symbols actually used */
     double *n1, *n2, *v;
+    double *K1, *K2;      /* box with a mean field: SEM matrices of V_ext + V_eff,j */
 } or_ctx;
 
 /* Rebuild the single-body symbols from the current density if the mean field
@@ -778,6 +809,22 @@ static void or_symbols(or_ctx* c, const double* f)
 {
     const or_grid* g = c->g;
     long nxk = (long)g->nx * g->nk;
+    if (!g->periodic) {
+        /* box: the SEM matrices of V_ext + V_eff,j (or_sem_kernel is linear in
+         * the potential), the Hartree term the direct convolution with V12 */
+        if (c->prm->lambda == 0.0 && !c->prm->xc) return;
+        long nk2 = nxk * g->nk;
+        double* kv = malloc(sizeof(double) * nk2);
+        or_densities(g, f, c->n1, c->n2);
+        or_veff_hxc(g, c->prm, c->tb->v12_pair, c->n1, c->v);
+        or_sem_kernel(g, c->v, kv);
+        for (long k = 0; k < nk2; ++k) c->K1[k] = c->tb->K[k] + kv[k];
+        or_veff_hxc(g, c->prm, c->tb->v12_pair, c->n2, c->v);
+        or_sem_kernel(g, c->v, kv);
+        for (long k = 0; k < nk2; ++k) c->K2[k] = c->tb->K[k] + kv[k];
+        free(kv);
+        return;
+    }
     memcpy(c->sig1, c->tb->sig_ext, sizeof(double) * nxk);
     memcpy(c->sig2, c->tb->sig_ext, sizeof(double) * nxk);
     if (c->prm->lambda == 0.0 && !c->prm->xc) return;
@@ -799,7 +846,8 @@ static void or_theta_all(or_ctx* c, const double* f, double* out)
     if (g->periodic)
         or_theta_periodic(g, c->sig1, c->sig2, c->tb->vhat12, c->prm->two_body, 0, np, f, out);
     else {
-        or_theta_dense(g, c->tb->K, c->tb->K, 0, np, f, out);
+        const int mf = c->prm->lambda != 0.0 || c->prm->xc;
+        or_theta_dense(g, mf ? c->K1 : c->tb->K, mf ? c->K2 : c->tb->K, 0, np, f, out);
         if (c->prm->two_body && c->tb->v12_sem) {
             long n = np * g->nk * g->nk;
             double* t = malloc(sizeof(double) * n);
@@ -824,21 +872,23 @@ int or_step(const or_grid* g, const or_params* prm, const or_tables* tb,
 {
     long N = (long)g->nx * g->nx * g->nk * g->nk;
     long nxk = (long)g->nx * g->nk;
+    const int box_mf = !g->periodic && (prm->lambda != 0.0 || prm->xc);
     or_ctx c = {g, prm, tb, malloc(sizeof(double) * nxk), malloc(sizeof(double) * nxk),
                 malloc(sizeof(double) * g->nx), malloc(sizeof(double) * g->nx),
-                malloc(sizeof(double) * g->nx)};
+                malloc(sizeof(double) * g->nx),
+                box_mf ? malloc(sizeof(double) * nxk * g->nk) : NULL,
+                box_mf ? malloc(sizeof(double) * nxk * g->nk) : NULL};
     double* k1 = malloc(sizeof(double) * N);
     double* k2 = malloc(sizeof(double) * N);
     double* t1 = malloc(sizeof(double) * N);
     double tau = prm->dt;
     int rc = 0;
-    if (!g->periodic && (prm->lambda != 0.0 || prm->xc)) rc = -2;
     for (long st = 0; st < nsteps && rc == 0; ++st) {
         if (prm->scheme == 0) {
             /* Strang: A(tau/2); Heun on Theta with the potential frozen at the
              * sub-step start; A(tau/2). */
             if (or_advect_both(g, 0.5 * tau, f, t1)) { rc = -1; break; }
-            if (g->periodic) or_symbols(&c, f);
+            or_symbols(&c, f);
             or_theta_all(&c, f, k1);
             for (long k = 0; k < N; ++k) t1[k] = f[k] + tau * k1[k];
             or_theta_all(&c, t1, k2);
@@ -848,17 +898,18 @@ int or_step(const or_grid* g, const or_params* prm, const or_tables* tb,
             /* Lawson predictor-corrector (Sec. 4.1):
              *   a = A_tau f, b = A_tau Theta[f], f~ = a + tau b,
              *   f+ = a + tau/2 Theta[f~] + tau/2 b. */
-            if (g->periodic) or_symbols(&c, f);
+            or_symbols(&c, f);
             or_theta_all(&c, f, k1);
             if (or_advect_both(g, tau, f, t1)) { rc = -1; break; }   /* f  <- a */
             if (or_advect_both(g, tau, k1, t1)) { rc = -1; break; }  /* k1 <- b */
             for (long k = 0; k < N; ++k) t1[k] = f[k] + tau * k1[k]; /* f~ */
-            if (g->periodic) or_symbols(&c, t1);
+            or_symbols(&c, t1);
             or_theta_all(&c, t1, k2);
             for (long k = 0; k < N; ++k) f[k] = f[k] + 0.5 * tau * k2[k] + 0.5 * tau * k1[k];
         }
     }
     free(c.sig1); free(c.sig2); free(c.n1); free(c.n2); free(c.v);
+    free(c.K1); free(c.K2);
     free(k1); free(k2); free(t1);
     return rc;
 }

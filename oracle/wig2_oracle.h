@@ -59,6 +59,7 @@ void or_veff_hxc(const or_grid* g, const or_params* prm, const double* v12_pair,
                  const double* n, double* v);
 void or_densities(const or_grid* g, const double* f, double* n1, double* n2);
 void or_hartree_poisson(const or_grid* g, const double* n, double* v);
+void or_hartree_padded(const or_grid* g, const double* v12_pad, const double* n, double* v);
 
 void or_theta_periodic(const or_grid* g, const double* sig1, const double* sig2,
                        const double* vhat12, int two_body,

@@ -519,6 +519,53 @@ def test_poisson_meanfield_chain_cosine(orc):
     assert np.abs(th - ex).max() <= 1e-9 * np.abs(ex).max()
 
 
+def test_hartree_padded_equals_direct_convolution(orc):
+    """Zero-padded box Hartree term (Sec. 3.2.1 remark): with 3nx points the
+    circular convolution of the padded transforms has no wrap-around, so it
+    equals the direct sum dx sum_j V12(x_m - x_j) n(x_j) term by term."""
+    g = orc.grid(33, 16, False, 2, -15.0, 15.0, 3.0)
+    x = orc.xnodes(g)
+    rng = np.random.default_rng(3)
+    n = np.exp(-(x - 1.0) ** 2 / 8) * (1 + 0.3 * rng.standard_normal(x.size))
+    v12 = I.smoothed_coulomb(1.3, 0.5)
+    vpad = np.array([v12(r) for r in orc.hartree_padded_points(g)])
+    got = orc.hartree_padded(g, vpad, n)
+    dx = x[1] - x[0]
+    ref = np.array([dx * sum(v12(x[m] - x[j]) * n[j] for j in range(x.size)) for m in range(x.size)])
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    # the box mean field of the oracle's steps uses that direct sum
+    vh = orc.veff_hxc(g, 1.0, False, 1.0, 1.0, np.vectorize(v12)(orc.pair_separations(g)), n)
+    assert np.abs(vh - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_box_meanfield_chain_closed_form(orc):
+    """The box branch of the mean-field chain on the Sec. 5.1.1 closed form:
+    box densities of f = pi^-2 e^{-(x1+r1)^2/2 - 2p1^2} e^{-(x2+r2)^2/2 - 2p2^2}
+    (SEM momentum weights), V_eff = n_j (lambda = 1, pair table I/dx), the SEM
+    matrix of V_eff, and Theta of both particles against
+    pi^{-5/2} e^{-3(x1+r1)^2/4 - p1^2} e^{-(x2+r2)^2/2 - 2p2^2} sin((x1+r1) p1) + (1 <-> 2),
+    on the Table-2 mesh (101 nodes on [-10, 10], 8 cells x 16 on [-5pi/2, 5pi/2])."""
+    r1, r2 = 1.0, -0.5
+    g = orc.grid(101, 128, False, 8, -10.0, 10.0, k_max=5 * np.pi / 2)
+    x = orc.xnodes(g)
+    p, _ = orc.pnodes(g)
+    X1, X2, P1, P2 = _mesh(x, p)
+    f = np.ascontiguousarray(np.pi**-2 * np.exp(-(X1 + r1) ** 2 / 2 - 2 * P1**2)
+                             * np.exp(-(X2 + r2) ** 2 / 2 - 2 * P2**2))
+    n1, n2 = orc.densities(g, f)
+    eye = np.eye(g.nx) / (x[1] - x[0])
+    v1 = orc.veff_hxc(g, 1.0, False, 1.0, 1.0, eye, n1)
+    v2 = orc.veff_hxc(g, 1.0, False, 1.0, 1.0, eye, n2)
+    assert np.abs(v1 - np.exp(-(x + r1) ** 2 / 2) / math.sqrt(2 * np.pi)).max() <= 1e-9  # SEM quadrature
+    K1, K2 = orc.sem_kernel(g, v1), orc.sem_kernel(g, v2)
+    th = orc.theta_dense(g, K1, K2, f)
+    ex = (np.pi**-2.5 * np.exp(-3 * (X1 + r1) ** 2 / 4 - P1**2) * np.exp(-(X2 + r2) ** 2 / 2 - 2 * P2**2)
+          * np.sin((X1 + r1) * P1)
+          + np.pi**-2.5 * np.exp(-3 * (X2 + r2) ** 2 / 4 - P2**2) * np.exp(-(X1 + r1) ** 2 / 2 - 2 * P1**2)
+          * np.sin((X2 + r2) * P2))
+    assert np.abs(th - ex).max() <= 1e-7 * np.abs(ex).max()
+
+
 def test_dense_theta_orientation_harmonic(orc):
     """or_theta_dense with the SEM matrix of V = omega^2 x^2 / 2 on both
     particles (Sec. 3.2.1): for a quadratic potential the Wigner operator is
