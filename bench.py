@@ -50,6 +50,10 @@ def kernel_model(name, npts, elem, nk, band, precision, dense=False, pair=False)
         return 2 * elem * npts, 20.0 * npts
     if name == "pair_sem":
         return 3 * elem * npts, 24.0 * nk * npts  # read x, read and write out
+    if name == "meanfield" and dense:
+        # plane integrals of the state, then both particles' SEM matrices:
+        # nx^2 nk^2 = npts terms of 7 flops (Im(E Q), two multiply-adds)
+        return elem * npts, 4.0 * npts + 7.0 * npts
     fl = (4.0 * nk if dense else theta_flops_per_point(nk, band)) * npts
     if pair:
         fl += 24.0 * nk * npts
@@ -433,12 +437,14 @@ def main():
                     help="default: fp64 for the single-grid workloads, fp32 for the ensemble")
     ap.add_argument("--scheme", default="strang", choices=["strang", "lawson"])
     ap.add_argument("--workload", default="large",
-                    choices=["large", "tiny", "ensemble", "box", "box-pair", "landau", "two-stream",
-                             "surrogate", "accuracy"],
+                    choices=["large", "tiny", "ensemble", "box", "box-pair", "box-meanfield", "landau",
+                             "two-stream", "surrogate", "accuracy"],
                     help="large: periodic 128^4 (default); tiny: periodic 32^4; ensemble: 64 "
                          "uneven periodic instances; box: 129^2 x 256^2 SEM box; box-pair: the "
                          "same box with the smoothed Coulomb pair potential (two-body SEM "
-                         "operator), FP64 by default; landau, two-stream: the Wigner-Poisson "
+                         "operator), FP64 by default; box-meanfield: box-pair with the "
+                         "Hartree mean field lambda = 1 (SEM matrices of V_ext + V_eff "
+                         "rebuilt per Theta sub-step); landau, two-stream: the Wigner-Poisson "
                          "workloads of Sec. 5 at 256^2 x 128^2 (neutralised Poisson Hartree, "
                          "pair potential 1/sqrt(r^2 + 1)), FP64; surrogate: "
                          "128^4 FP32 with the learned pair increment; accuracy: FP32 and "
@@ -475,10 +481,10 @@ def main():
         return bench_surrogate(a)
     if a.workload == "accuracy":
         return bench_accuracy(a)
-    box = a.workload in ("box", "box-pair")
+    box = a.workload in ("box", "box-pair", "box-meanfield")
     a.precision = a.precision or ("fp32" if a.workload == "box" else "fp64")
     if box:
-        w = I.box_sem(129, 16, 16, a.potential, pair_u=1.0 if a.workload == "box-pair" else None)
+        w = I.box_sem(129, 16, 16, a.potential, pair_u=None if a.workload == "box" else 1.0)
     elif a.workload in ("landau", "two-stream"):
         w = I.plasma(a.workload, 256, 128)
     else:
@@ -497,7 +503,8 @@ def main():
 
     forms = [f for f in a.forms.split(",") if f] if (a.workload == "large" and a.precision == "fp64") else []
     main_leg = run_form(w, f0, box, a.scheme, a.precision, a.steps, a.warmup,
-                        keep_state=bool(forms), copy_calibration=a.copy_calibration,
+                        lam=1.0 if a.workload == "box-meanfield" else 0.0, keep_state=bool(forms),
+                        copy_calibration=a.copy_calibration,
                         gpu_samples=not a.no_cpu and a.workload == "large" and a.precision == "fp64")
     cpu = None
     if not a.no_cpu and a.workload == "large" and a.precision == "fp64":
@@ -530,7 +537,7 @@ def main():
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": main_leg["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[a.precision], "data": "synthetic",
-        "config": {"workload": w.name, "nx": w.nx, "nk": w.nk, "points": w.points, "dt": w.dt,
+        "config": {"workload": w.name + ("-meanfield" if a.workload == "box-meanfield" else ""), "nx": w.nx, "nk": w.nk, "points": w.points, "dt": w.dt,
                    "scheme": a.scheme, "precision": a.precision, "V12_U": w.extra.get("U", 1.0),
                    "single_body_band": main_leg["band"], "theta_kernel": main_leg["theta_kernel"],
                    "seed": 0},
@@ -548,7 +555,8 @@ def make_solver(w, box, scheme, precision, lam=0.0):
 
     if box:
         return wig2.Solver(w.nx, w.nk, periodic=False, sem_cells=w.cells, x_min=w.x_min,
-                           x_max=w.x_max, k_max=w.k_max, dt=w.dt, scheme=scheme, precision=precision)
+                           x_max=w.x_max, k_max=w.k_max, dt=w.dt, scheme=scheme, precision=precision,
+                           meanfield_lambda=lam)
     if "hartree" in w.extra:  # the plasma workloads: their own mean field
         s = wig2.Solver(w.nx, w.nk, x_min=w.x_min, x_max=w.x_max, dt=w.dt, scheme=scheme,
                         precision=precision, meanfield_lambda=w.extra["lam"])

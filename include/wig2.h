@@ -87,7 +87,11 @@ typedef struct {
  *                   particle j (the (N-k)/(N-1) prefactor of Sec. 2.1; 0 for N=2).
  *  xc               1: add the Hedin-Lundqvist potential (Sec. 2.2) in atomic
  *                   units, evaluated at n_scale * n_j(x), minus its value at xc_n0.
- *  Mean field (lambda != 0 or xc) is supported on the torus only. */
+ *  Mean field (lambda != 0 or xc): on the torus V_eff,j enters particle j's
+ *  symbol; on a box (Sec. 3.2.1) particle j's SEM matrices become those of
+ *  V_ext + V_eff,j, rebuilt on the device before every Theta evaluation
+ *  (the Hartree term is the direct convolution dx sum_l V12(x_i - x_l) n_l,
+ *  equal to the zero-padded transform on 3 nx points, no wrap-around). */
 typedef struct {
     double hbar, mass, dt;
     int32_t scheme, precision;

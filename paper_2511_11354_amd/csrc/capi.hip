@@ -69,6 +69,11 @@ struct wig2_ctx {
     int hartree = WIG2_HARTREE_PAIR;
     double* hart_d = nullptr;  // [nx][nx] Hartree kernel of the mean field
     float* ksem_f = nullptr;  // FP32 copy of the SEM matrices (nk = 256, FP32 / BF16X2)
+    // box with a mean field: the SEM matrices of V_ext + V_eff,j per particle,
+    // rebuilt from the factor tables on every update
+    double *kmf1_d = nullptr, *kmf2_d = nullptr, *semE_d = nullptr, *semQ_d = nullptr;
+    float *kmf1_f = nullptr, *kmf2_f = nullptr;
+    double sem_pref = 0.0;
     // box with a pair potential: the two-body SEM operator's tables (element
     // type of the state), its per-chunk workspaces and a state-sized
     // accumulator for calls whose output aliases an input
@@ -263,6 +268,14 @@ ThetaArgs theta_args(wig2_ctx* c)
     a.ksem_t = nullptr;
     if (!c->g.periodic && c->g.nk == kPanelThetaNk)
         a.ksem_t = c->elem == 8 ? (const void*)c->ksem_d : (const void*)c->ksem_f;
+    if (!c->g.periodic && c->meanfield) {
+        a.ksem = c->kmf1_d;
+        a.ksem2 = c->kmf2_d;
+        if (c->g.nk == kPanelThetaNk) {
+            a.ksem_t = c->elem == 8 ? (const void*)c->kmf1_d : (const void*)c->kmf1_f;
+            a.ksem2_t = c->elem == 8 ? (const void*)c->kmf2_d : (const void*)c->kmf2_f;
+        }
+    }
     return a;
 }
 
@@ -345,8 +358,15 @@ hipError_t update_meanfield(wig2_ctx* c, const T* a, const T* b, double tau_b)
         e = moments<T>(c, b, c->s0b_d, nullptr, nullptr, nullptr);
         if (e != hipSuccess) return e;
     }
-    return launch_meanfield(mf_args(c), c->s0_d, b ? c->s0b_d : nullptr, tau_b, c->sig1_d, c->sig2_d,
-                            c->st);
+    if (c->g.periodic)
+        return launch_meanfield(mf_args(c), c->s0_d, b ? c->s0b_d : nullptr, tau_b, c->sig1_d, c->sig2_d, c->st);
+    // box: V_eff,j, then the SEM matrices of V_ext + V_eff,j
+    e = launch_meanfield_potential(mf_args(c), c->s0_d, b ? c->s0b_d : nullptr, tau_b, c->st);
+    if (e != hipSuccess) return e;
+    const int nodes = c->g.nk / c->g.cells;
+    const SemMfArgs sa{c->g.nx, c->g.nk, nodes, c->sem_pref, c->ksem_d, c->mf_veff_d,
+                       c->semE_d, c->semQ_d, c->kmf1_d, c->kmf2_d};
+    return launch_meanfield_sem(sa, c->kmf1_f, c->kmf2_f, c->st);
 }
 
 // One step of the Lawson predictor-corrector (Sec. 4.1):
@@ -885,7 +905,6 @@ int wig2_create(const wig2_grid* grid, const wig2_params* prm, void* hip_stream,
     const bool panel = !G.periodic && G.nk == kPanelThetaNk;
     if (!theta_nk_ok(G.nk) && !panel) return WIG2_ENOTSUP;
     if (P.precision == WIG2_BF16X2 && G.nk % 32 != 0) return WIG2_ENOTSUP;
-    if (!G.periodic && (P.meanfield_lambda != 0.0 || P.xc)) return WIG2_ENOTSUP;
     if (!G.periodic && !panel && P.precision == WIG2_BF16X2) return WIG2_ENOTSUP;
 
     wig2_ctx* c = new (std::nothrow) wig2_ctx();
@@ -929,6 +948,17 @@ int wig2_create(const wig2_grid* grid, const wig2_params* prm, void* hip_stream,
         return bail(WIG2_ENOMEM);
     if (!G.periodic && dev_alloc(c, &c->ksem_d, (size_t)nx * nk * nk)) return bail(WIG2_ENOMEM);
     if (panel && c->elem == 4 && dev_alloc(c, &c->ksem_f, (size_t)nx * nk * nk)) return bail(WIG2_ENOMEM);
+    if (!G.periodic && c->meanfield) {
+        std::vector<double> E, Q;
+        host_sem_factors(c->g, E, Q, c->sem_pref);
+        if (dev_alloc(c, &c->kmf1_d, (size_t)nx * nk * nk) || dev_alloc(c, &c->kmf2_d, (size_t)nx * nk * nk) ||
+            dev_alloc(c, &c->semE_d, E.size()) || dev_alloc(c, &c->semQ_d, Q.size()))
+            return bail(WIG2_ENOMEM);
+        if (panel && c->elem == 4 &&
+            (dev_alloc(c, &c->kmf1_f, (size_t)nx * nk * nk) || dev_alloc(c, &c->kmf2_f, (size_t)nx * nk * nk)))
+            return bail(WIG2_ENOMEM);
+        if (upload(c, c->semE_d, E) || upload(c, c->semQ_d, Q)) return bail(WIG2_EDEVICE);
+    }
 
     host_nodes(c->g, c->x, c->p, c->w);
     c->pmax = 0.0;
@@ -958,7 +988,8 @@ void wig2_destroy(wig2_ctx* c)
     if (!c) return;
     if (c->st) hipStreamSynchronize(c->st);
     void* bufs[] = {c->f_own, c->k1, c->tmp, c->work, c->p_d, c->w_d, c->thomas_d, c->sig_ext_d, c->sig1_d,
-                    c->sig2_d, c->kap_d, c->ksem_d, c->ksem_f, c->v12pair_d, c->hart_d, c->sintab_d,
+                    c->sig2_d, c->kap_d, c->ksem_d, c->ksem_f, c->kmf1_d, c->kmf2_d, c->kmf1_f, c->kmf2_f,
+                    c->semE_d, c->semQ_d, c->v12pair_d, c->hart_d, c->sintab_d,
                     c->mf_dens_d, c->mf_veff_d, c->s0_d, c->s0b_d, c->skin_d, c->s2_d, c->rows_d,
                     c->f1_d, c->ft, c->fs, c->sur_buf, c->s12_wa, c->s12_wb, c->s12_wc, c->s12_wd,
                     c->s12_dt, c->s12_wr, c->s12_wh, c->s12_acc};
@@ -1084,6 +1115,19 @@ int wig2_set_potentials(wig2_ctx* c, wig2_fn1 v_ext, wig2_fn1 v12, void* user)
             const std::vector<float> Kf(K.begin(), K.end());
             HIPCHK(c, hipMemcpyAsync(c->ksem_f, Kf.data(), Kf.size() * sizeof(float), hipMemcpyHostToDevice, c->st));
             HIPCHK(c, hipStreamSynchronize(c->st));
+        }
+        if (c->kmf1_d) {
+            // the mean field's matrices start as those of V_ext (every step
+            // rebuilds them before its first Theta)
+            if (upload(c, c->kmf1_d, K) || upload(c, c->kmf2_d, K)) return WIG2_EDEVICE;
+            if (c->kmf1_f) {
+                const std::vector<float> Kf(K.begin(), K.end());
+                HIPCHK(c, hipMemcpyAsync(c->kmf1_f, Kf.data(), Kf.size() * sizeof(float), hipMemcpyHostToDevice,
+                                         c->st));
+                HIPCHK(c, hipMemcpyAsync(c->kmf2_f, Kf.data(), Kf.size() * sizeof(float), hipMemcpyHostToDevice,
+                                         c->st));
+                HIPCHK(c, hipStreamSynchronize(c->st));
+            }
         }
         c->two_body = false;
         c->band = nk;

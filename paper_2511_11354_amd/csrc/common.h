@@ -36,6 +36,10 @@ void host_pair_kernel(const GridInfo& g, const std::vector<double>& v12_r,
                       std::vector<double>& vhat, std::vector<double>& kap);
 // Box single-body SEM matrices K[i][n][n'] from V at the x nodes.
 void host_sem_matrix(const GridInfo& g, const std::vector<double>& v_x, std::vector<double>& K);
+// Factors of that operator over the node distance d = i - j in [-(nx-1), nx-1]:
+// E[(d + nx - 1)][n][s] = e^{2 i (p_n - d_s) d dx / hbar}, Q[(d + nx - 1)][k] =
+// Q_k(-h d dx / hbar) (complex, re/im pairs), K = pref sum_j V_j Im(E Q).
+void host_sem_factors(const GridInfo& g, std::vector<double>& E, std::vector<double>& Q, double& pref);
 // Box two-body operator (Sec. 3.2.2): y-lattice spacing dy = pi hbar / |P|
 // (|P| = 2 hbar k_max) and the real operands of its four matrix products
 // (layouts in tables.cpp), from vs[l + nx - 1][d + nk - 1] = V12(l dx + d dy).
@@ -81,6 +85,10 @@ struct ThetaArgs {
     const double* ksem;
     int precision;  // WIG2_FP64 / WIG2_FP32 / WIG2_BF16X2
     const void* ksem_t;  // box, nk = 256: SEM matrices in the state's element type
+    // box with a mean field: particle 2's SEM matrices (particle 1's are
+    // ksem / ksem_t); NULL: both particles use ksem / ksem_t
+    const double* ksem2 = nullptr;
+    const void* ksem2_t = nullptr;
 };
 template <typename T>
 hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, double tau,
@@ -211,6 +219,23 @@ struct MeanFieldArgs {
 };
 hipError_t launch_meanfield(const MeanFieldArgs& a, const double* s0, const double* s0b,
                             double tau_b, double* sig1, double* sig2, hipStream_t st);
+// The density and effective-potential part alone (box contexts).
+hipError_t launch_meanfield_potential(const MeanFieldArgs& a, const double* s0, const double* s0b, double tau_b,
+                                      hipStream_t st);
+// Box mean field: SEM matrices of V_ext + V_eff,j for both particles (FP64,
+// plus FP32 copies when k1f is given) from veff [2][nx] and the factor
+// tables E [(2nx-1)][nk][M] and Q [(2nx-1)][N] (complex, re/im pairs).
+struct SemMfArgs {
+    int nx, nk, nodes;
+    double pref;
+    const double* kext;  // [nx][nk][nk] SEM matrices of V_ext
+    const double* veff;  // [2][nx]
+    const double* E;
+    const double* Q;
+    double* k1;
+    double* k2;
+};
+hipError_t launch_meanfield_sem(const SemMfArgs& a, float* k1f, float* k2f, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Batched ensembles: one launch per phase walks a work list over all

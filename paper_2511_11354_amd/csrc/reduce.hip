@@ -171,7 +171,54 @@ __global__ void k_meanfield_symbols(MeanFieldArgs a, double* __restrict__ sig1,
     sig2[id] = a.sig_ext[id] + h2;
 }
 
+// Box mean field (Sec. 3.2.1): the SEM matrices of V_ext + V_eff,j.  The SEM
+// single-body operator is linear in the potential, and its kernel factorises
+// over the node distance d = i - l (tables from the host):
+//   K_j[i][n][s N + k] = kext[i][n][s N + k]
+//                        + pref sum_l V_j(x_l) Im(E[d][n][s] Q[d][k]).
+template <typename T>
+__global__ __launch_bounds__(256) void k_meanfield_sem(SemMfArgs a, T* __restrict__ k1t, T* __restrict__ k2t)
+{
+    const int nx = a.nx, nk = a.nk, N = a.nodes, M = nk / N;
+    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long)nx * nk * nk) return;
+    const int i = (int)(id / ((long)nk * nk));
+    const int rem = (int)(id % ((long)nk * nk));
+    const int n = rem / nk, c = rem % nk, s = c / N, k = c % N;
+    double acc1 = 0.0, acc2 = 0.0;
+    for (int l = 0; l < nx; ++l) {
+        const int d = i - l + nx - 1;
+        const double* e = a.E + 2 * (((long)d * nk + n) * M + s);
+        const double* q = a.Q + 2 * ((long)d * N + k);
+        const double im = e[0] * q[1] + e[1] * q[0];
+        acc1 += a.veff[l] * im;
+        acc2 += a.veff[nx + l] * im;
+    }
+    const double v1 = a.kext[id] + a.pref * acc1, v2 = a.kext[id] + a.pref * acc2;
+    a.k1[id] = v1;
+    a.k2[id] = v2;
+    if (k1t) {
+        k1t[id] = T(v1);
+        k2t[id] = T(v2);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_meanfield_potential(const MeanFieldArgs& a, const double* s0, const double* s0b, double tau_b,
+                                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_meanfield_potential, dim3(1), dim3(256), 0, st, a, s0, s0b, tau_b);
+    return hipGetLastError();
+}
+
+hipError_t launch_meanfield_sem(const SemMfArgs& a, float* k1f, float* k2f, hipStream_t st)
+{
+    const long n = (long)a.nx * a.nk * a.nk;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_meanfield_sem<float>, dim3(nb), dim3(256), 0, st, a, k1f, k2f);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_plane_moments(const T* f, int nx, int nk, const double* p_dev,

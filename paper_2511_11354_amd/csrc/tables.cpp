@@ -285,6 +285,42 @@ void host_sem12_tables(const GridInfo& g, const std::vector<double>& vs, Sem12Ta
             t.dtab[(size_t)l * nd + d + ny - 1] = c * (vs[(size_t)l * nd + d + ny - 1] - vs[(size_t)l * nd - d + ny - 1]);
 }
 
+// The factors of host_sem_matrix's kernel over the node distance, for the
+// mean field's matrices rebuilt on the device.
+void host_sem_factors(const GridInfo& g, std::vector<double>& E, std::vector<double>& Q, double& pref)
+{
+    const int nx = g.nx, nk = g.nk, M = g.cells, N = nk / M;
+    const double hb = g.hbar, dx = g.dx();
+    const double pm = hb * g.k_max, h = 2.0 * pm / M;
+    std::vector<double> x, p, w, eta, bw;
+    host_nodes(g, x, p, w);
+    cheb_nodes(N, eta, bw);
+    const int nd = 2 * nx - 1;
+    Q.assign((size_t)2 * nd * N, 0.0);
+    E.assign((size_t)2 * nd * nk * M, 0.0);
+    for (int d = -(nx - 1); d <= nx - 1; ++d) {
+        const double zeta = -h * d * dx / hb;
+        const int q = std::max(48, (int)std::ceil(std::fabs(zeta)) + 2 * N + 40);
+        std::vector<double> gx, gw;
+        gauss_legendre(q, gx, gw);
+        const size_t di = (size_t)(d + nx - 1);
+        for (int k = 0; k < N; ++k) {
+            cplx acc(0.0, 0.0);
+            for (int t = 0; t < q; ++t) acc += gw[t] * cardinal(eta, bw, k, gx[t]) * std::polar(1.0, zeta * gx[t]);
+            Q[2 * (di * N + k)] = acc.real();
+            Q[2 * (di * N + k) + 1] = acc.imag();
+        }
+        for (int n = 0; n < nk; ++n)
+            for (int s = 0; s < M; ++s) {
+                const double ds = -pm + h * (s + 0.5);
+                const cplx e = std::polar(1.0, 2.0 * (p[n] - ds) * d * dx / hb);
+                E[2 * ((di * nk + n) * M + s)] = e.real();
+                E[2 * ((di * nk + n) * M + s) + 1] = e.imag();
+            }
+    }
+    pref = 2.0 * dx / (kPi * hb * hb) * 0.5 * h;
+}
+
 // 1-RDM from the reduced Wigner function (Appendix B):
 //   rho1(x_{mu-nu}, x_{mu+nu}) = sum_n w_n f1(x_mu, p_n) e^{-2 i p_n nu dx / hbar},
 // on the even sub-lattice (all mid-points on the grid).  Eigenvalues of the

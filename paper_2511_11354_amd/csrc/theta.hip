@@ -62,7 +62,8 @@ struct PlaneJob {
     const double* sig1;
     const double* sig2;
     const double* kap;
-    const double* ksem;
+    const double* ksem;   // SEM matrices of particle 1 (box)
+    const double* ksem2;  // of particle 2
     int band;
     double tau;
 };
@@ -86,6 +87,7 @@ __device__ __forceinline__ void theta_plane(const PlaneJob<T>& J, T* smem, int t
     const double* __restrict__ sig2 = J.sig2;
     const double* __restrict__ kap = J.kap;
     const double* __restrict__ ksem = J.ksem;
+    const double* __restrict__ ksem2 = J.ksem2;
 
     T* Xbase = smem;
     T* X = Xbase + kPadFront;            // X[r * LD + c]
@@ -159,7 +161,7 @@ __device__ __forceinline__ void theta_plane(const PlaneJob<T>& J, T* smem, int t
 
         if constexpr (SEM) {
             const double* K1 = ksem + (long)i1 * NK * NK;
-            const double* K2 = ksem + (long)i2 * NK * NK;
+            const double* K2 = ksem2 + (long)i2 * NK * NK;
     #pragma unroll 1
             for (int kb = 0; kb < NK / 4; ++kb) {
                 const int k = 4 * kb + lk;
@@ -273,13 +275,13 @@ template <typename T, int NK, bool TWO, bool SEM, int MODE>
 __global__ __launch_bounds__(NK / 16 * 64 * planes_per_block<NK>()) void k_theta(
     const T* u, const T* __restrict__ vin, T* out, int nx, long np, const double* __restrict__ sig1,
     const double* __restrict__ sig2, int band, const double* __restrict__ kap,
-    const double* __restrict__ ksem, double tau)
+    const double* __restrict__ ksem, const double* __restrict__ ksem2, double tau)
 {
     constexpr int NT = NK / 16 * 64;
     extern __shared__ unsigned char smem_raw[];
     const int g = threadIdx.x / NT;
     const long pl = (long)blockIdx.x * planes_per_block<NK>() + g;
-    PlaneJob<T> J{u, vin, out, pl, nx, sig1, sig2, kap, ksem, band, tau};
+    PlaneJob<T> J{u, vin, out, pl, nx, sig1, sig2, kap, ksem, ksem2, band, tau};
     T* smem = reinterpret_cast<T*>(smem_raw) + (size_t)g * (Plane<T, NK>::bytes / sizeof(T));
     theta_plane<T, NK, TWO, SEM, MODE>(J, smem, threadIdx.x % NT, pl < np);
 }
@@ -302,7 +304,7 @@ __device__ __forceinline__ void theta_batch_item(const T* u_pool, const T* v_poo
     const bool active = g < item.np;
     PlaneJob<T> J{u_pool + I.off, v_pool ? v_pool + I.off : nullptr, out_pool + I.off,
                   (long)item.plane0 + g, I.nx, sig_pool + I.tab_off, sig_pool + I.tab_off,
-                  kap_pool + I.tab_off, nullptr, I.band, I.tau};
+                  kap_pool + I.tab_off, nullptr, nullptr, I.band, I.tau};
     T* slice = smem + (size_t)(active ? g : 0) * (Plane<T, NK>::bytes / sizeof(T));
     if (I.two_body)
         theta_plane<T, NK, true, false, MODE>(J, slice, threadIdx.x % NT, active);
@@ -564,12 +566,12 @@ hipError_t go(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, doub
         auto kf = k_theta<T, NK, TWO, SEM, 0>;
         hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
         hipLaunchKernelGGL(kf, dim3(nb), blk, sm, st, u, v, out, a.nx, np, a.sig1, a.sig2, band,
-                           a.kap, a.ksem, tau);
+                           a.kap, a.ksem, a.ksem2 ? a.ksem2 : a.ksem, tau);
     } else {
         auto kf = k_theta<T, NK, TWO, SEM, 1>;
         hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
         hipLaunchKernelGGL(kf, dim3(nb), blk, sm, st, u, v, out, a.nx, np, a.sig1, a.sig2, band,
-                           a.kap, a.ksem, tau);
+                           a.kap, a.ksem, a.ksem2 ? a.ksem2 : a.ksem, tau);
     }
     return hipGetLastError();
 }

@@ -74,7 +74,7 @@ __device__ inline long xcd_block(long b, long G)
 template <typename T, int NK, int FORM>
 __global__ __launch_bounds__((PanelLayout<T, NK>::NT)) void k_theta_panel(const T* x, const T* y, T* out,
                                                                         int nx, const T* __restrict__ kmat,
-                                                                        double tau)
+                                                                        const T* __restrict__ kmat2, double tau)
 {
     typedef typename Acc<T>::V V;
     typedef PanelLayout<T, NK> L;
@@ -98,7 +98,7 @@ __global__ __launch_bounds__((PanelLayout<T, NK>::NT)) void k_theta_panel(const 
     const long pbase = pl * (long)NK * NK;
     const T* F = x + pbase;
     const T* K1 = kmat + (long)i1 * NK * NK;
-    const T* K2 = kmat + (long)i2 * NK * NK;
+    const T* K2 = kmat2 + (long)i2 * NK * NK;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -220,7 +220,8 @@ struct PanelBf16Layout {
 
 template <int NK, int FORM>
 __global__ __launch_bounds__((PanelBf16Layout<NK>::NT)) void k_theta_panel_bf16(
-    const float* x, const float* y, float* out, int nx, const float* __restrict__ kmat, double tau)
+    const float* x, const float* y, float* out, int nx, const float* __restrict__ kmat,
+    const float* __restrict__ kmat2, double tau)
 {
     typedef PanelBf16Layout<NK> L;
     constexpr int RB = L::RB, NT = L::NT;
@@ -249,7 +250,7 @@ __global__ __launch_bounds__((PanelBf16Layout<NK>::NT)) void k_theta_panel_bf16(
     const long pbase = pl * (long)NK * NK;
     const float* F = x + pbase;
     const float* K1 = kmat + (long)i1 * NK * NK;
-    const float* K2 = kmat + (long)i2 * NK * NK;
+    const float* K2 = kmat2 + (long)i2 * NK * NK;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -367,7 +368,8 @@ hipError_t go_panel(const ThetaArgs& a, const T* x, const T* y, T* out, double t
             if (e != hipSuccess) return e;
             const long nb = np * (NK / PanelBf16Layout<NK>::NC);
             hipLaunchKernelGGL(kf, dim3((unsigned)nb), dim3(PanelBf16Layout<NK>::NT), sm, st, x, y, out,
-                               a.nx, reinterpret_cast<const float*>(a.ksem_t), tau);
+                               a.nx, reinterpret_cast<const float*>(a.ksem_t),
+                               reinterpret_cast<const float*>(a.ksem2_t ? a.ksem2_t : a.ksem_t), tau);
             return hipGetLastError();
         }
     }
@@ -377,7 +379,8 @@ hipError_t go_panel(const ThetaArgs& a, const T* x, const T* y, T* out, double t
     if (e != hipSuccess) return e;
     const long nb = np * (NK / PanelLayout<T, NK>::NC);
     hipLaunchKernelGGL(kf, dim3((unsigned)nb), dim3(PanelLayout<T, NK>::NT), sm, st, x, y, out, a.nx,
-                       reinterpret_cast<const T*>(a.ksem_t), tau);
+                       reinterpret_cast<const T*>(a.ksem_t),
+                       reinterpret_cast<const T*>(a.ksem2_t ? a.ksem2_t : a.ksem_t), tau);
     return hipGetLastError();
 }
 

@@ -53,8 +53,8 @@ def test_strerror_codes():
     (dict(nx=16, nk=32, periodic=0, sem_cells=4, k_max=0.0), {}, wig2.EINVAL),
     (dict(nx=16, nk=40), {}, wig2.ENOTSUP),                    # not a Theta tile size
     (dict(nx=16, nk=48), dict(precision=wig2.BF16X2), wig2.ENOTSUP),
-    (dict(nx=16, nk=32, periodic=0, sem_cells=4, k_max=3.0), dict(meanfield_lambda=1.0),
-     wig2.ENOTSUP),
+    (dict(nx=16, nk=32, periodic=0, sem_cells=4, k_max=3.0), dict(precision=wig2.BF16X2),
+     wig2.ENOTSUP),                                            # BF16X2 box needs the panel size
 ])
 def test_create_rejects_before_device_work(grid, params, code):
     L = wig2.lib()
