@@ -70,11 +70,20 @@ struct StreamLayout {
 };
 
 // Waves per SIMD to budget registers for: FP32 planes of 128 fit twice in
-// LDS, so two 8-wave workgroups share a CU when a wave stays within 128 VGPRs.
+// LDS, so two 8-wave workgroups share a CU when a wave stays within 128 VGPRs
+// (the one-pass Heun form then drops its register prefetch of the next plane:
+// the other workgroup's matrix-core work covers the loads; 4% faster than one
+// workgroup with the prefetch, bitwise the same).
 template <typename T, int NK, int FORM, int WS>
 constexpr int stream_waves_per_eu()
 {
-    return (sizeof(T) == 4 && NK == 128 && FORM != 3 && WS == 1) ? 4 : (sizeof(T) == 4 && NK <= 64) ? 2 : 1;
+    return (sizeof(T) == 4 && NK == 128 && WS == 1) ? 4 : (sizeof(T) == 4 && NK <= 64) ? 2 : 1;
+}
+// The batched kernel loads each plane at the top of its loop.
+template <typename T, int NK>
+constexpr int batch_stream_waves_per_eu()
+{
+    return (sizeof(T) == 4 && NK <= 64) ? 2 : 1;
 }
 
 // Theta work on one plane held in LDS (X, and tk for the pair term), after
@@ -400,12 +409,12 @@ __global__ __launch_bounds__(NK / 16 * 64 * WS, (stream_waves_per_eu<T, NK, FORM
         return t;
     };
     // The one-pass Heun form prefetches the first NVP loads of the next
-    // plane during its second pass (at nk = 128: all of them for FP32, half
-    // for FP64, whose second pass has no room for the whole plane in
-    // registers; none at smaller planes, where the spare registers buy more
-    // resident waves instead) and issues the rest at the top of the next
-    // iteration.
-    constexpr int NVP = FORM != 3 ? NV : NK != 128 ? 0 : sizeof(T) == 8 ? NV / 2 : NV;
+    // plane during its second pass (at nk = 128 FP64: half of them, the
+    // second pass has no room for the whole plane in registers; none for
+    // FP32 at 128, which runs two workgroups per CU instead, nor at smaller
+    // planes, where the spare registers buy more resident waves) and issues
+    // the rest at the top of the next iteration.
+    constexpr int NVP = FORM != 3 ? NV : (NK == 128 && sizeof(T) == 8) ? NV / 2 : 0;
     auto fetch_range = [&](long p, int v0, int v1) {
         const VT* src = reinterpret_cast<const VT*>(x + p * (long)NK * NK);
         const int ot = opaque_tid();
@@ -511,7 +520,7 @@ hipError_t go_stream_nk(const ThetaArgs& a, const T* x, const T* y, T* out, int 
 // in place (the same per-plane arithmetic as a single context).
 // ---------------------------------------------------------------------------
 template <typename T, int NK>
-__global__ __launch_bounds__(NK / 16 * 64, (stream_waves_per_eu<T, NK, 3, 1>())) void k_theta_stream_batch(
+__global__ __launch_bounds__(NK / 16 * 64, (batch_stream_waves_per_eu<T, NK>())) void k_theta_stream_batch(
     T* pool, const BatchInst* __restrict__ insts,
                                                                    const ThItem* __restrict__ items, int nitems,
                                                                    const double* __restrict__ sig_pool,
