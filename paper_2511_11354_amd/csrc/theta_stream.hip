@@ -236,6 +236,34 @@ __device__ __forceinline__ void stream_plane(const T* y, T* out, int nx, long pl
             el = opaque_lane();
             const T s1 = T(sig1[(long)i1 * NK + m]);
             const T s2 = T(sig2[(long)i2 * NK + m]);
+            if constexpr (sizeof(T) == 4 && NK < 128) {
+                if (m == 1) {
+                    // FP32 tiles put a lane's four points on consecutive
+                    // rows of one anti-diagonal, (n1 + q, n2 - q), so their
+                    // 16 neighbours at distance 1 are 10 distinct values:
+                    // rm[t] = f(n1 + t, n2 - t - 1), t = -1..3, and
+                    // rp[t] = f(n1 + t, n2 - t + 1), t = 0..4, at fixed
+                    // offsets t (LD - 1) -+ 1 from the first point (4-6%
+                    // faster launches at nk = 64, 96; at 128, whose one-pass
+                    // Heun form runs at 128 VGPRs, the extra live values
+                    // spill and it measured 7% slower).
+#pragma unroll
+                    for (int j = 0; j < NSH; ++j) {
+                        const T* b = lds_at(j, 0);
+                        T rm[5], rp[5];
+#pragma unroll
+                        for (int t = 0; t < 5; ++t) {
+                            rm[t] = b[(t - 1) * (LD - 1) - 1];
+                            rp[t] = b[t * (LD - 1) + 1];
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            acc[j][q] += s1 * (rm[q] - rp[q + 1]) + s2 * (rm[q + 1] - rp[q]);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    continue;
+                }
+            }
 #pragma unroll
             for (int j = 0; j < NSH; ++j) {
 #pragma unroll
