@@ -450,6 +450,11 @@ hipError_t heun_theta(wig2_ctx* c, T* x, T* out)
         if ((e = THS(x, nullptr, k1, 1)) != hipSuccess) return e;
         return THS(k1, x, out, 2);
     }
+    // general kernel: the whole Heun step in one pass where it has that form
+    // (torus, nk = 128), else its two stages
+    if (theta_heun_general_ok(theta_args(c)))
+        return timed(c, WIG2_PROF_THETA_HEUN,
+                     [&] { return launch_theta_heun<T>(theta_args(c), x, out, tau, c->st); });
     if ((e = TH(x, nullptr, k1, 0)) != hipSuccess) return e;
     return TH(x, k1, out, 1);
 }

@@ -93,6 +93,11 @@ struct ThetaArgs {
 template <typename T>
 hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, double tau,
                         hipStream_t st);
+// One-pass Heun step of the general kernel (torus, nk = 128, FP64 / FP32):
+// out = x + (tau/2)(Theta x + Theta (x + tau Theta x)); out may alias x.
+bool theta_heun_general_ok(const ThetaArgs& a);
+template <typename T>
+hipError_t launch_theta_heun(const ThetaArgs& a, const T* x, T* out, double tau, hipStream_t st);
 
 // Box two-body operator (theta12_sem.hip).  Tables in the state's element
 // type: wa (nk x 2nk), wb (2nk x 2nk), wc (2nk x 2nk), wd (2nk x nk), dtab

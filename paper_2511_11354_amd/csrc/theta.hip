@@ -263,6 +263,199 @@ __device__ __forceinline__ void theta_plane(const PlaneJob<T>& J, T* smem, int t
     __syncthreads();  // the LDS slice may be reused by the next plane
 }
 
+// ---------------------------------------------------------------------------
+// One-pass Heun step on the general kernel (torus, nk = 128, dense or banded
+// single-body symbols): out = f + (tau/2)(Theta f + Theta g), g = f + tau
+// Theta f, with the potentials frozen over the step (Strang's sub-step), in
+// one pass over the plane instead of the two stage launches, which read the
+// state four times and write it twice.  Theta acts within the plane, so the
+// plane stays in LDS between the two applications:
+//   pass 1   regular tiles acc = K1 f + f K2^T, skewed tiles sacc = Theta_12 f;
+//            sacc scattered into the LDS plane; at each lane's regular points
+//            Theta f = acc + LDS, f re-read from the input;
+//            FP64: acc = h = f + (tau/2) Theta f, LDS = (tau/2) g;
+//            FP32: hv = h kept apart, LDS = g (accumulating onto h in FP32
+//            rounds at the scale of f once per matrix-core instruction);
+//   pass 2   the same products of the LDS plane (onto h in FP64), the pair
+//            tiles scattered again, out = h + (tau/2) Theta g.
+// out may alias f: every point is re-read and written by the same lane.
+// ---------------------------------------------------------------------------
+template <typename T, int NK, bool TWO>
+__device__ __forceinline__ void theta_plane_heun(const PlaneJob<T>& J, T* smem, int tid)
+{
+    typedef typename Acc<T>::V V;
+    typedef Plane<T, NK> P;
+    constexpr int NW = NK / 16;
+    constexpr int LD = P::LD;
+    constexpr int NT = NW * 64;
+    constexpr int NS = NW + 1;
+    constexpr bool ONTO_H = sizeof(T) == 8;
+
+    const T* u = J.u;
+    T* out = J.out;
+    const int nx = J.nx, band = J.band;
+    const double tau = J.tau;
+    const double* __restrict__ sig1 = J.sig1;
+    const double* __restrict__ sig2 = J.sig2;
+    const double* __restrict__ kap = J.kap;
+
+    T* Xbase = smem;
+    T* X = Xbase + kPadFront;
+    T* t1 = Xbase + P::X_ELEMS;
+    T* t2 = t1 + P::TAB;
+    T* tk = t2 + P::TAB;
+
+    const long pl = J.pl;
+    const int i1 = (int)(pl / nx), i2 = (int)(pl % nx);
+    const int ell = (i1 - i2 + nx) % nx;
+    const long pbase = pl * (long)NK * NK;
+
+    const int lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int r = 16 * w + li;
+
+    for (int e = tid; e < 2 * NK; e += NT) {
+        const int d = e - NK, ad = d < 0 ? -d : d;
+        const bool ok = ad > 0 && ad < NK;
+        t1[e] = !ok ? T(0) : sgnval(d, T(sig1[(long)i1 * NK + ad]));
+        t2[e] = !ok ? T(0) : sgnval(d, T(sig2[(long)i2 * NK + ad]));
+        tk[e] = (!TWO || !ok) ? T(0) : sgnval(d, T(kap[(long)ell * NK + ad]));
+    }
+    for (int e = tid; e < kPadFront; e += NT) Xbase[e] = T(0);
+    for (int e = tid; e < NK * kPadCols; e += NT) X[(e / kPadCols) * LD + NK + e % kPadCols] = T(0);
+    {
+        T xr[NW][4];
+#pragma unroll
+        for (int cb = 0; cb < NW; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                xr[cb][q] = u[pbase + (long)(16 * w + acc_row<T>(lk, q)) * NK + 16 * cb + li];
+#pragma unroll
+        for (int cb = 0; cb < NW; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) X[(16 * w + acc_row<T>(lk, q)) * LD + 16 * cb + li] = xr[cb][q];
+    }
+    __syncthreads();
+
+    // acc += K1 X + X K2^T (the single-body symbols vanish beyond `band` modes)
+    auto single = [&](V (&acc)[NW]) {
+        const int kb1_lo = max(0, 16 * w - band) / 4;
+        const int kb1_hi = min(NK - 1, 16 * w + 15 + band) / 4;
+        const T* pa1 = t1 + r + NK - lk;
+        const T* pb1 = X + lk * LD + li;
+#pragma unroll 2
+        for (int kb = kb1_lo; kb <= kb1_hi; ++kb) {
+            const T a1 = pa1[-4 * kb];
+#pragma unroll
+            for (int cb = 0; cb < NW; ++cb) acc[cb] = mma(a1, pb1[4 * kb * LD + 16 * cb], acc[cb]);
+        }
+        const T* pa2 = X + r * LD + lk;
+        const T* pb2 = t2 + li + NK - lk;
+#pragma unroll 2
+        for (int kb = 0; kb < NK / 4; ++kb) {
+            const T a2 = pa2[4 * kb];
+#pragma unroll
+            for (int cb = 0; cb < NW; ++cb) {
+                if (4 * kb + 3 < 16 * cb - band || 4 * kb > 16 * cb + 15 + band) continue;
+                acc[cb] = mma(a2, pb2[16 * cb - 4 * kb], acc[cb]);
+            }
+        }
+    };
+    // sacc = Theta_12 X on the skewed tiles, then scattered into X once every
+    // wave is done reading it
+    auto pair_to_lds = [&](V (&sacc)[NS]) {
+        if constexpr (TWO) {
+#pragma unroll
+            for (int j = 0; j < NS; ++j) sacc[j] = V{0, 0, 0, 0};
+            const T* pa = tk + r + NK - lk;
+            const T* pb = X + lk * (LD - 1) + 16 * w + li;
+#pragma unroll 2
+            for (int kb = 0; kb < NK / 4; ++kb) {
+                const T a = pa[-4 * kb];
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    const int s0 = 16 * (w + j);
+                    if (4 * kb + 3 < s0 - NK + 1 || 4 * kb > s0 + 15) continue;  // wave-uniform
+                    sacc[j] = mma(a, pb[4 * kb * (LD - 1) + 16 * j], sacc[j]);
+                }
+            }
+        }
+        __syncthreads();  // every wave is done reading the plane
+        if constexpr (TWO) {
+#pragma unroll
+            for (int j = 0; j < NS; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int n1 = 16 * w + acc_row<T>(lk, q);
+                    const int n2 = 16 * (w + j) + li - n1;
+                    if (n2 >= 0 && n2 < NK) X[n1 * LD + n2] = sacc[j][q];
+                }
+            __syncthreads();
+        }
+    };
+
+    V acc[NW];
+    V sacc[NS];
+#pragma unroll
+    for (int cb = 0; cb < NW; ++cb) acc[cb] = V{0, 0, 0, 0};
+    single(acc);
+    pair_to_lds(sacc);
+
+    // pass-1 epilogue at the lane's regular points
+    V hv[ONTO_H ? 1 : NW];
+#pragma unroll
+    for (int cb = 0; cb < NW; ++cb) {
+        const int c = 16 * cb + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int rr = 16 * w + acc_row<T>(lk, q);
+            T th = acc[cb][q];
+            if constexpr (TWO) th += X[rr * LD + c];
+            const T fv = u[pbase + (long)rr * NK + c];
+            if constexpr (ONTO_H) {
+                acc[cb][q] = fv + T(0.5 * tau) * th;
+                X[rr * LD + c] = T(0.5 * tau) * (fv + T(tau) * th);
+            } else {
+                hv[cb][q] = fv + T(0.5 * tau) * th;
+                acc[cb][q] = T(0);
+                X[rr * LD + c] = fv + T(tau) * th;
+            }
+        }
+    }
+    __syncthreads();
+
+    single(acc);
+    pair_to_lds(sacc);
+#pragma unroll
+    for (int cb = 0; cb < NW; ++cb) {
+        const int c = 16 * cb + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int rr = 16 * w + acc_row<T>(lk, q);
+            T th = acc[cb][q];
+            if constexpr (TWO) th += X[rr * LD + c];
+            const long gi = pbase + (long)rr * NK + c;
+            if constexpr (ONTO_H)
+                out[gi] = th;
+            else
+                out[gi] = hv[cb][q] + T(0.5 * tau) * th;
+        }
+    }
+}
+
+template <typename T, int NK, bool TWO>
+__global__ __launch_bounds__(NK / 16 * 64) void k_theta_heun(const T* u, T* out, int nx, long np,
+                                                            const double* __restrict__ sig1,
+                                                            const double* __restrict__ sig2, int band,
+                                                            const double* __restrict__ kap, double tau)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const long pl = blockIdx.x;
+    if (pl >= np) return;  // whole workgroup leaves together
+    PlaneJob<T> J{u, nullptr, out, pl, nx, sig1, sig2, kap, nullptr, nullptr, band, tau};
+    theta_plane_heun<T, NK, TWO>(J, reinterpret_cast<T*>(smem_raw), threadIdx.x);
+}
+
 // Planes per workgroup for the single-context launch: small planes share a
 // workgroup so that a workgroup has up to 8 waves.
 template <int NK>
@@ -640,6 +833,29 @@ hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int 
     }
 }
 
+
+bool theta_heun_general_ok(const ThetaArgs& a)
+{
+    return a.nk == 128 && !a.ksem && a.precision != WIG2_BF16X2;
+}
+
+template <typename T>
+hipError_t launch_theta_heun(const ThetaArgs& a, const T* x, T* out, double tau, hipStream_t st)
+{
+    if (!theta_heun_general_ok(a)) return hipErrorNotSupported;
+    constexpr int NK = 128;
+    const long np = (long)a.nx * a.nx;
+    const size_t sm = Plane<T, NK>::bytes;
+    const int band = std::min(a.band, NK - 1);
+    auto kf = a.kap ? k_theta_heun<T, NK, true> : k_theta_heun<T, NK, false>;
+    hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kf, dim3((unsigned)np), dim3(NK / 16 * 64), sm, st, x, out, a.nx, np, a.sig1, a.sig2,
+                       band, a.kap, tau);
+    return hipGetLastError();
+}
+template hipError_t launch_theta_heun<double>(const ThetaArgs&, const double*, double*, double, hipStream_t);
+template hipError_t launch_theta_heun<float>(const ThetaArgs&, const float*, float*, double, hipStream_t);
 
 bool batch_nk_ok(int nk) { return nk == 16 || nk == 32 || nk == 48 || nk == 64 || nk == 96 || nk == 128; }
 

@@ -48,6 +48,8 @@ def kernel_class(name: str):
     if m:
         cls = {0: "theta_apply", 1: "theta_stage1", 2: "theta_stage2"}[int(m.group(2))]
         return cls, os.path.join(CSRC, "theta_panel.hip")
+    if n.startswith("k_theta_heun<"):
+        return "theta_heun", os.path.join(CSRC, "theta.hip")
     m = re.match(r"k_theta<(\w+), (\d+), (\w+), (\w+), (\d)>", n)
     if m:
         return ("theta_stage1" if m.group(5) == "0" else "theta_stage2"), os.path.join(CSRC, "theta.hip")
