@@ -337,27 +337,64 @@ __device__ __forceinline__ void theta_plane_heun(const PlaneJob<T>& J, T* smem, 
     }
     __syncthreads();
 
-    // acc += K1 X + X K2^T (the single-body symbols vanish beyond `band` modes)
+    // acc += K1 X + X K2^T (the single-body symbols vanish beyond `band` modes).
+    // Operands of k-step kb + 1 are read from LDS while the matrix cores work
+    // on k-step kb (two register sets).
     auto single = [&](V (&acc)[NW]) {
+        T a[2], b[2][NW];
+        // K1 X: K1[r][k] = t1[r - k + NK], rows within band of this wave
         const int kb1_lo = max(0, 16 * w - band) / 4;
         const int kb1_hi = min(NK - 1, 16 * w + 15 + band) / 4;
         const T* pa1 = t1 + r + NK - lk;
         const T* pb1 = X + lk * LD + li;
-#pragma unroll 2
-        for (int kb = kb1_lo; kb <= kb1_hi; ++kb) {
-            const T a1 = pa1[-4 * kb];
+        auto ld1 = [&](int kb, int buf) {
+            a[buf] = pa1[-4 * kb];
 #pragma unroll
-            for (int cb = 0; cb < NW; ++cb) acc[cb] = mma(a1, pb1[4 * kb * LD + 16 * cb], acc[cb]);
+            for (int cb = 0; cb < NW; ++cb) b[buf][cb] = pb1[4 * kb * LD + 16 * cb];
+        };
+        auto mm = [&](int buf) {
+#pragma unroll
+            for (int cb = 0; cb < NW; ++cb) acc[cb] = mma(a[buf], b[buf][cb], acc[cb]);
+        };
+        int kb = kb1_lo;
+        ld1(kb, 0);
+        for (; kb + 1 <= kb1_hi; kb += 2) {
+            ld1(kb + 1, 1);
+            mm(0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (kb + 2 <= kb1_hi) ld1(kb + 2, 0);
+            mm(1);
+            __builtin_amdgcn_sched_barrier(0);
         }
+        if (kb <= kb1_hi) mm(0);
+        // X K2^T: K2[c][k] = t2[c - k + NK]
         const T* pa2 = X + r * LD + lk;
         const T* pb2 = t2 + li + NK - lk;
-#pragma unroll 2
-        for (int kb = 0; kb < NK / 4; ++kb) {
-            const T a2 = pa2[4 * kb];
+        if (band >= NK - 1) {
+            // dense symbols: every (k-step, column block) pair, no tests
+            auto ld2 = [&](int k, int buf) {
+                a[buf] = pa2[4 * k];
 #pragma unroll
-            for (int cb = 0; cb < NW; ++cb) {
-                if (4 * kb + 3 < 16 * cb - band || 4 * kb > 16 * cb + 15 + band) continue;
-                acc[cb] = mma(a2, pb2[16 * cb - 4 * kb], acc[cb]);
+                for (int cb = 0; cb < NW; ++cb) b[buf][cb] = pb2[16 * cb - 4 * k];
+            };
+            ld2(0, 0);
+            for (int k = 0; k < NK / 4; k += 2) {
+                ld2(k + 1, 1);
+                mm(0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (k + 2 < NK / 4) ld2(k + 2, 0);
+                mm(1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll 2
+            for (int k = 0; k < NK / 4; ++k) {
+                const T a2 = pa2[4 * k];
+#pragma unroll
+                for (int cb = 0; cb < NW; ++cb) {
+                    if (4 * k + 3 < 16 * cb - band || 4 * k > 16 * cb + 15 + band) continue;
+                    acc[cb] = mma(a2, pb2[16 * cb - 4 * k], acc[cb]);
+                }
             }
         }
     };
@@ -367,16 +404,33 @@ __device__ __forceinline__ void theta_plane_heun(const PlaneJob<T>& J, T* smem, 
         if constexpr (TWO) {
 #pragma unroll
             for (int j = 0; j < NS; ++j) sacc[j] = V{0, 0, 0, 0};
-            const T* pa = tk + r + NK - lk;
-            const T* pb = X + lk * (LD - 1) + 16 * w + li;
-#pragma unroll 2
-            for (int kb = 0; kb < NK / 4; ++kb) {
-                const T a = pa[-4 * kb];
+            // over the k-block offset d = KB - w: the A operand depends on d
+            // alone and the tiles j meeting k-block KB = w + d are
+            // j in [max(0, d), min(NW, d + NW)], fixed per d; operands of the
+            // next k-step read during the current one
+            const T* pa0 = tk + li + NK - lk;
+            const T* pb0 = X + lk * (LD - 1) + 16 * w * LD + li;
+            T a[2], bv[2][NS];
 #pragma unroll
-                for (int j = 0; j < NS; ++j) {
-                    const int s0 = 16 * (w + j);
-                    if (4 * kb + 3 < s0 - NK + 1 || 4 * kb > s0 + 15) continue;  // wave-uniform
-                    sacc[j] = mma(a, pb[4 * kb * (LD - 1) + 16 * j], sacc[j]);
+            for (int d = -(NW - 1); d <= NW - 1; ++d) {
+                if (w + d < 0 || w + d >= NW) continue;  // wave-uniform
+                const int lo = d < 0 ? 0 : d, hi = d < 0 ? d + NW : NW;
+                auto ldp = [&](int i, int buf) {
+                    a[buf] = pa0[-16 * d - 4 * i];
+                    const T* pb = pb0 + (16 * d + 4 * i) * (LD - 1);
+#pragma unroll
+                    for (int j = 0; j < NS; ++j)
+                        if (j >= lo && j <= hi) bv[buf][j] = pb[16 * j];
+                };
+                ldp(0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int cur = i & 1;
+                    if (i + 1 < 4) ldp(i + 1, cur ^ 1);
+#pragma unroll
+                    for (int j = 0; j < NS; ++j)
+                        if (j >= lo && j <= hi) sacc[j] = mma(a[cur], bv[cur][j], sacc[j]);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }
