@@ -451,7 +451,7 @@ hipError_t heun_theta(wig2_ctx* c, T* x, T* out)
         return THS(k1, x, out, 2);
     }
     // general kernel: the whole Heun step in one pass where it has that form
-    // (torus, nk = 128), else its two stages
+    // (torus), else its two stages
     if (theta_heun_general_ok(theta_args(c)))
         return timed(c, WIG2_PROF_THETA_HEUN,
                      [&] { return launch_theta_heun<T>(theta_args(c), x, out, tau, c->st); });

@@ -264,8 +264,8 @@ __device__ __forceinline__ void theta_plane(const PlaneJob<T>& J, T* smem, int t
 }
 
 // ---------------------------------------------------------------------------
-// One-pass Heun step on the general kernel (torus, nk = 128, dense or banded
-// single-body symbols): out = f + (tau/2)(Theta f + Theta g), g = f + tau
+// One-pass Heun step on the general kernel (torus, any supported nk, dense
+// or banded single-body symbols): out = f + (tau/2)(Theta f + Theta g), g = f + tau
 // Theta f, with the potentials frozen over the step (Strang's sub-step), in
 // one pass over the plane instead of the two stage launches, which read the
 // state four times and write it twice.  Theta acts within the plane, so the
@@ -888,16 +888,19 @@ hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int 
 }
 
 
+// nk = 16 keeps the two stages: it is the plane size whose batched classes
+// take the general kernel, and batched instances step bitwise as single
+// contexts (the batched general kernel is the two-stage one).
 bool theta_heun_general_ok(const ThetaArgs& a)
 {
-    return a.nk == 128 && !a.ksem && a.precision != WIG2_BF16X2;
+    const bool nk_ok = a.nk == 32 || a.nk == 48 || a.nk == 64 || a.nk == 96 || a.nk == 128;
+    return nk_ok && !a.ksem && a.precision != WIG2_BF16X2;
 }
 
-template <typename T>
-hipError_t launch_theta_heun(const ThetaArgs& a, const T* x, T* out, double tau, hipStream_t st)
+namespace {
+template <typename T, int NK>
+hipError_t go_heun(const ThetaArgs& a, const T* x, T* out, double tau, hipStream_t st)
 {
-    if (!theta_heun_general_ok(a)) return hipErrorNotSupported;
-    constexpr int NK = 128;
     const long np = (long)a.nx * a.nx;
     const size_t sm = Plane<T, NK>::bytes;
     const int band = std::min(a.band, NK - 1);
@@ -907,6 +910,20 @@ hipError_t launch_theta_heun(const ThetaArgs& a, const T* x, T* out, double tau,
     hipLaunchKernelGGL(kf, dim3((unsigned)np), dim3(NK / 16 * 64), sm, st, x, out, a.nx, np, a.sig1, a.sig2,
                        band, a.kap, tau);
     return hipGetLastError();
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_theta_heun(const ThetaArgs& a, const T* x, T* out, double tau, hipStream_t st)
+{
+    if (!theta_heun_general_ok(a)) return hipErrorNotSupported;
+    switch (a.nk) {
+    case 32: return go_heun<T, 32>(a, x, out, tau, st);
+    case 48: return go_heun<T, 48>(a, x, out, tau, st);
+    case 64: return go_heun<T, 64>(a, x, out, tau, st);
+    case 96: return go_heun<T, 96>(a, x, out, tau, st);
+    default: return go_heun<T, 128>(a, x, out, tau, st);
+    }
 }
 template hipError_t launch_theta_heun<double>(const ThetaArgs&, const double*, double*, double, hipStream_t);
 template hipError_t launch_theta_heun<float>(const ThetaArgs&, const float*, float*, double, hipStream_t);

@@ -1,10 +1,10 @@
-"""The one-pass Heun step of the general Theta kernel (torus, nk = 128):
+"""The one-pass Heun step of the general Theta kernel (torus, nk = 32..128):
 out = f + (tau/2)(Theta f + Theta g), g = f + tau Theta f, with the plane kept
 in LDS between the two applications (pair tiles scattered through it, f
 re-read at each lane's points), against the FP64 oracle's Strang steps and
-against the streaming kernel's Heun step.  It serves every Strang step at
-nk = 128 whose single-body band is too wide for the streaming kernel (the
-mean field, dense potentials) and the forced "general" path.
+against the streaming kernel's Heun step.  It serves every Strang step
+whose single-body band is too wide for the streaming kernel (the mean field,
+dense potentials) and the forced "general" path.
 
 FP64 bar: eps_inf = max|f - f_ref| / max|f_ref| <= 1e-12; FP32: 2e-5 after
 3 steps (the streaming FP32 path's bound).
@@ -72,6 +72,28 @@ def test_general_heun_fp32(orc):
     e = eps_inf(s.get_state(), ref)
     print(f"general heun fp32 lam=1: 3 steps eps_inf {e:.3e}", flush=True)
     assert e <= 2e-5
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("scheme", ["strang", "lawson"])
+@pytest.mark.parametrize("nx,nk", [(12, 32), (9, 48), (8, 64), (6, 96)])
+def test_general_heun_smaller_planes(orc, nx, nk, scheme):
+    """The one-pass form at every other plane size it serves (Strang; Lawson
+    keeps the two stages), with the Hartree mean field (dense symbols)."""
+    from paper_2511_11354_amd import wig2
+
+    s = wig2.Solver(nx, nk, dt=0.005, scheme=scheme, meanfield_lambda=1.0)
+    s.set_potentials(VEXT["cos"], V12)
+    x, p, _ = s.nodes()
+    f0 = I.mixture(x, p, seed=3 + nk, period=20.0)
+    s.set_state(f0)
+    assert s.theta_path() == "general"
+    g = orc.grid(nx, nk, True, 1, -10.0, 10.0)
+    s.step(3)
+    ref = orc.step(g, f0, orc.tables(g, VEXT["cos"], V12), 3, 0.005, scheme=scheme, lam=1.0)
+    e = eps_inf(s.get_state(), ref)
+    print(f"general heun {scheme} {nx}^2 x {nk}^2 lam=1: 3 steps eps_inf {e:.3e}", flush=True)
+    assert e <= 1e-12
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
