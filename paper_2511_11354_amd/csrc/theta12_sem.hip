@@ -79,6 +79,17 @@ __global__ __launch_bounds__(256) void k_sem12_gemm(const T* __restrict__ A, con
         const T* A2b = XPY ? A2 + b * sA : nullptr;
         const T* Bb = B + b * sB;
         T* Cb = C + b * sC;
+        // D_l row of this plane's pair distance l = i1 - i2, and the row
+        // offset of the tile within the y-lattice: r % ny = r0 % ny + (r - r0),
+        // less ny once past it (tiles are at most 64 rows, ny >= 32)
+        const T* drow = nullptr;
+        int rmod0 = 0;
+        if constexpr (EPI == 1) {
+            const long pl = plane0 + b;
+            const int l = (int)(pl / nx) - (int)(pl % nx);
+            drow = dtab + (long)(l + nx - 1) * (2 * ny - 1) + ny - 1;
+            rmod0 = r0 % ny;
+        }
         for (int c0 = 0; c0 < N; c0 += TN) {
             V acc[MT][NT];
 #pragma unroll
@@ -86,19 +97,24 @@ __global__ __launch_bounds__(256) void k_sem12_gemm(const T* __restrict__ A, con
 #pragma unroll
                 for (int j = 0; j < NT; ++j) acc[i][j] = V{0, 0, 0, 0};
             T ra[AV], rb[BV];
-            auto fetch = [&](int k0) {
+            // per-thread operand pointers, advanced by one K step per stage:
+            // A element (r0 + tid / kKT + 256 v / kKT, tid % kKT + k0),
+            // B element (tid / TN + 256 v / TN + k0, c0 + tid % TN)
+            const T* pa = Ab + (long)(r0 + tid / kKT) * K + tid % kKT;
+            const T* pa2 = XPY ? A2b + (long)(r0 + tid / kKT) * K + tid % kKT : nullptr;
+            const T* pbb = Bb + (long)(tid / TN) * N + c0 + tid % TN;
+            constexpr int AROWS = 256 / kKT, BROWS = 256 / TN;
+            auto fetch = [&](int) {
 #pragma unroll
                 for (int v = 0; v < AV; ++v) {
-                    const int e = tid + 256 * v, r = e / kKT, k = e % kKT;
-                    const long gi = (long)(r0 + r) * K + k0 + k;
-                    ra[v] = Ab[gi];
-                    if constexpr (XPY) ra[v] += T(beta) * A2b[gi];
+                    ra[v] = pa[(long)v * AROWS * K];
+                    if constexpr (XPY) ra[v] += T(beta) * pa2[(long)v * AROWS * K];
                 }
 #pragma unroll
-                for (int v = 0; v < BV; ++v) {
-                    const int e = tid + 256 * v, k = e / TN, c = e % TN;
-                    rb[v] = Bb[(long)(k0 + k) * N + c0 + c];
-                }
+                for (int v = 0; v < BV; ++v) rb[v] = pbb[(long)v * BROWS * N];
+                pa += kKT;
+                if constexpr (XPY) pa2 += kKT;
+                pbb += (long)kKT * N;
             };
             auto stash = [&](int buf) {
                 T* As = lds + buf * L::STAGE;
@@ -152,9 +168,9 @@ __global__ __launch_bounds__(256) void k_sem12_gemm(const T* __restrict__ A, con
                         const long gi = (long)r * N + c;
                         T v = acc[i][j][q];
                         if constexpr (EPI == 1) {
-                            const long pl = plane0 + b;
-                            const int l = (int)(pl / nx) - (int)(pl % nx);
-                            v *= dtab[(long)(l + nx - 1) * (2 * ny - 1) + (r % ny) - c + ny - 1];
+                            int rm = rmod0 + (r - r0);
+                            rm = rm >= ny ? rm - ny : rm;
+                            v *= drow[rm - c];
                             Cb[gi] = v;
                         } else if constexpr (EPI == 2) {
                             Cb[gi] += T(alpha) * v;
