@@ -47,6 +47,160 @@ using namespace mf;
 
 
 // ---------------------------------------------------------------------------
+// Products shared by the two-stage and the one-pass Heun plane bodies, on the
+// plane X in LDS (pitch Plane<T, NK>::LD) and the signed Toeplitz tables.
+// Operands of the next k-step are read from LDS while the matrix cores work
+// on the current one (two register sets).
+// ---------------------------------------------------------------------------
+// acc += K1 X + X K2^T on the regular tiles of row block w (symbols vanishing
+// beyond `band` modes; dense symbols take no per-instruction tests)
+// PIPE = false (workgroups of more than 8 waves, 128 registers a wave, and
+// the batched kernel, whose work-list loop leaves no room for the second
+// register set): one register set, the k-step loop unrolled twice.
+template <typename T, int NK, bool PIPE = true>
+__device__ __forceinline__ void single_products(typename Acc<T>::V (&acc)[NK / 16], const T* X, const T* t1,
+                                                const T* t2, int w, int li, int lk, int band)
+{
+    constexpr int NW = NK / 16;
+    constexpr int LD = Plane<T, NK>::LD;
+    const int r = 16 * w + li;
+    if constexpr (!PIPE) {
+        const int kb1_lo = max(0, 16 * w - band) / 4;
+        const int kb1_hi = min(NK - 1, 16 * w + 15 + band) / 4;
+        const T* pa1 = t1 + r + NK - lk;
+        const T* pb1 = X + lk * LD + li;
+#pragma unroll 2
+        for (int kb = kb1_lo; kb <= kb1_hi; ++kb) {
+            const T a1 = pa1[-4 * kb];
+#pragma unroll
+            for (int cb = 0; cb < NW; ++cb) acc[cb] = mma(a1, pb1[4 * kb * LD + 16 * cb], acc[cb]);
+        }
+        const T* pa2 = X + r * LD + lk;
+        const T* pb2 = t2 + li + NK - lk;
+#pragma unroll 2
+        for (int kb = 0; kb < NK / 4; ++kb) {
+            const T a2 = pa2[4 * kb];
+#pragma unroll
+            for (int cb = 0; cb < NW; ++cb) {
+                if (4 * kb + 3 < 16 * cb - band || 4 * kb > 16 * cb + 15 + band) continue;
+                acc[cb] = mma(a2, pb2[16 * cb - 4 * kb], acc[cb]);
+            }
+        }
+        return;
+    }
+    T a[2], b[2][NW];
+    auto mm = [&](int buf) {
+#pragma unroll
+        for (int cb = 0; cb < NW; ++cb) acc[cb] = mma(a[buf], b[buf][cb], acc[cb]);
+    };
+    // K1 X: K1[r][k] = t1[r - k + NK], rows within band of this wave
+    const int kb1_lo = max(0, 16 * w - band) / 4;
+    const int kb1_hi = min(NK - 1, 16 * w + 15 + band) / 4;
+    const T* pa1 = t1 + r + NK - lk;
+    const T* pb1 = X + lk * LD + li;
+    auto ld1 = [&](int kb, int buf) {
+        a[buf] = pa1[-4 * kb];
+#pragma unroll
+        for (int cb = 0; cb < NW; ++cb) b[buf][cb] = pb1[4 * kb * LD + 16 * cb];
+    };
+    int kb = kb1_lo;
+    ld1(kb, 0);
+    for (; kb + 1 <= kb1_hi; kb += 2) {
+        ld1(kb + 1, 1);
+        mm(0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (kb + 2 <= kb1_hi) ld1(kb + 2, 0);
+        mm(1);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (kb <= kb1_hi) mm(0);
+    // X K2^T: K2[c][k] = t2[c - k + NK]
+    const T* pa2 = X + r * LD + lk;
+    const T* pb2 = t2 + li + NK - lk;
+    if (band >= NK - 1) {
+        auto ld2 = [&](int k, int buf) {
+            a[buf] = pa2[4 * k];
+#pragma unroll
+            for (int cb = 0; cb < NW; ++cb) b[buf][cb] = pb2[16 * cb - 4 * k];
+        };
+        ld2(0, 0);
+        for (int k = 0; k < NK / 4; k += 2) {
+            ld2(k + 1, 1);
+            mm(0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (k + 2 < NK / 4) ld2(k + 2, 0);
+            mm(1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+#pragma unroll 2
+        for (int k = 0; k < NK / 4; ++k) {
+            const T a2 = pa2[4 * k];
+#pragma unroll
+            for (int cb = 0; cb < NW; ++cb) {
+                if (4 * k + 3 < 16 * cb - band || 4 * k > 16 * cb + 15 + band) continue;
+                acc[cb] = mma(a2, pb2[16 * cb - 4 * k], acc[cb]);
+            }
+        }
+    }
+}
+
+// sacc (+)= Theta_12 X on the skewed tiles (n1, s = n1 + n2) of row block w,
+// over the k-block offset d = KB - w: the A operand depends on d alone and
+// the tiles meeting k-block KB = w + d are j in [max(0, d), min(NW, d + NW)],
+// fixed per d, so one wave-uniform test per k-block.  A = tk[r - k + NK],
+// B = X[k LD + s - k] (zero gaps outside the plane).
+template <typename T, int NK, bool PIPE = true>
+__device__ __forceinline__ void pair_products(typename Acc<T>::V (&sacc)[NK / 16 + 1], const T* X, const T* tk,
+                                              int w, int li, int lk)
+{
+    constexpr int NW = NK / 16;
+    constexpr int NS = NW + 1;
+    constexpr int LD = Plane<T, NK>::LD;
+    if constexpr (!PIPE) {
+        // per k-step, the tiles whose anti-diagonals meet its rows
+        const T* pa = tk + 16 * w + li + NK - lk;
+        const T* pb = X + lk * (LD - 1) + 16 * w + li;
+#pragma unroll 2
+        for (int kb = 0; kb < NK / 4; ++kb) {
+            const T a = pa[-4 * kb];
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                const int s0 = 16 * (w + j);
+                if (4 * kb + 3 < s0 - NK + 1 || 4 * kb > s0 + 15) continue;  // wave-uniform
+                sacc[j] = mma(a, pb[4 * kb * (LD - 1) + 16 * j], sacc[j]);
+            }
+        }
+        return;
+    }
+    const T* pa0 = tk + li + NK - lk;
+    const T* pb0 = X + lk * (LD - 1) + 16 * w * LD + li;
+    T a[2], bv[2][NS];
+#pragma unroll
+    for (int d = -(NW - 1); d <= NW - 1; ++d) {
+        if (w + d < 0 || w + d >= NW) continue;  // wave-uniform
+        const int lo = d < 0 ? 0 : d, hi = d < 0 ? d + NW : NW;
+        auto ldp = [&](int i, int buf) {
+            a[buf] = pa0[-16 * d - 4 * i];
+            const T* pb = pb0 + (16 * d + 4 * i) * (LD - 1);
+#pragma unroll
+            for (int j = 0; j < NS; ++j)
+                if (j >= lo && j <= hi) bv[buf][j] = pb[16 * j];
+        };
+        ldp(0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int cur = i & 1;
+            if (i + 1 < 4) ldp(i + 1, cur ^ 1);
+#pragma unroll
+            for (int j = 0; j < NS; ++j)
+                if (j >= lo && j <= hi) sacc[j] = mma(a[cur], bv[cur][j], sacc[j]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // FP64 / FP32 plane body.  One group of NK/16 waves handles one plane with
 // its own LDS slice; several groups (planes) may share a workgroup.  Every
 // thread of the workgroup calls the body with the same template arguments
@@ -68,7 +222,7 @@ struct PlaneJob {
     double tau;
 };
 
-template <typename T, int NK, bool TWO, bool SEM, int MODE>
+template <typename T, int NK, bool TWO, bool SEM, int MODE, bool PIPE>
 __device__ __forceinline__ void theta_plane(const PlaneJob<T>& J, T* smem, int tid, bool active)
 {
     typedef typename Acc<T>::V V;
@@ -175,51 +329,13 @@ __device__ __forceinline__ void theta_plane(const PlaneJob<T>& J, T* smem, int t
                 }
             }
         } else {
-            // K1 F: K1[r][k] = t1[r - k + NK] vanishes for |r - k| > band, so only
-            // the k blocks within band of this wave's rows contribute.
-            const int kb1_lo = max(0, 16 * w - band) / 4;
-            const int kb1_hi = min(NK - 1, 16 * w + 15 + band) / 4;
-            const T* pa1 = t1 + r + NK - lk;  // t1[r - (4kb + lk) + NK] = pa1[-4kb]
-            const T* pb1 = X + lk * LD + li;  // X[(4kb + lk) LD + 16cb + li]
-    #pragma unroll 2
-            for (int kb = kb1_lo; kb <= kb1_hi; ++kb) {
-                const T a1 = pa1[-4 * kb];
-    #pragma unroll
-                for (int cb = 0; cb < NW; ++cb) acc[cb] = mma(a1, pb1[4 * kb * LD + 16 * cb], acc[cb]);
-            }
-            // F K2^T: K2[c][k] = t2[c - k + NK] vanishes for |c - k| > band.
-            const T* pa2 = X + r * LD + lk;          // X[r][4kb + lk]
-            const T* pb2 = t2 + li + NK - lk;        // t2[16cb + li - 4kb - lk + NK]
-    #pragma unroll 2
-            for (int kb = 0; kb < NK / 4; ++kb) {
-                const T a2 = pa2[4 * kb];
-    #pragma unroll
-                for (int cb = 0; cb < NW; ++cb) {
-                    if (4 * kb + 3 < 16 * cb - band || 4 * kb > 16 * cb + 15 + band) continue;
-                    acc[cb] = mma(a2, pb2[16 * cb - 4 * kb], acc[cb]);
-                }
-            }
+            single_products<T, NK, PIPE>(acc, X, t1, t2, w, li, lk, band);
         }
 
         if constexpr (TWO) {
     #pragma unroll
             for (int j = 0; j < NS; ++j) sacc[j] = V{0, 0, 0, 0};
-            // skewed tile j covers s in [s0, s0 + 16), s0 = 16(w + j); H[n1'][s]
-            // is non-zero for n1' in [s - NK + 1, s], so block kb contributes when
-            // 4kb + 3 >= s0 - NK + 1 and 4kb <= s0 + 15.  Operand addresses:
-            // A = tk[r - k + NK], B = X[k LD + s0 + li - k] (zero gaps outside).
-            const T* pa = tk + r + NK - lk;
-            const T* pb = X + lk * (LD - 1) + 16 * w + li;
-    #pragma unroll 2
-            for (int kb = 0; kb < NK / 4; ++kb) {
-                const T a = pa[-4 * kb];
-    #pragma unroll
-                for (int j = 0; j < NS; ++j) {
-                    const int s0 = 16 * (w + j);
-                    if (4 * kb + 3 < s0 - NK + 1 || 4 * kb > s0 + 15) continue;  // wave-uniform
-                    sacc[j] = mma(a, pb[4 * kb * (LD - 1) + 16 * j], sacc[j]);
-                }
-            }
+            pair_products<T, NK, PIPE>(sacc, X, tk, w, li, lk);
         }
 
     }
@@ -337,102 +453,14 @@ __device__ __forceinline__ void theta_plane_heun(const PlaneJob<T>& J, T* smem, 
     }
     __syncthreads();
 
-    // acc += K1 X + X K2^T (the single-body symbols vanish beyond `band` modes).
-    // Operands of k-step kb + 1 are read from LDS while the matrix cores work
-    // on k-step kb (two register sets).
-    auto single = [&](V (&acc)[NW]) {
-        T a[2], b[2][NW];
-        // K1 X: K1[r][k] = t1[r - k + NK], rows within band of this wave
-        const int kb1_lo = max(0, 16 * w - band) / 4;
-        const int kb1_hi = min(NK - 1, 16 * w + 15 + band) / 4;
-        const T* pa1 = t1 + r + NK - lk;
-        const T* pb1 = X + lk * LD + li;
-        auto ld1 = [&](int kb, int buf) {
-            a[buf] = pa1[-4 * kb];
-#pragma unroll
-            for (int cb = 0; cb < NW; ++cb) b[buf][cb] = pb1[4 * kb * LD + 16 * cb];
-        };
-        auto mm = [&](int buf) {
-#pragma unroll
-            for (int cb = 0; cb < NW; ++cb) acc[cb] = mma(a[buf], b[buf][cb], acc[cb]);
-        };
-        int kb = kb1_lo;
-        ld1(kb, 0);
-        for (; kb + 1 <= kb1_hi; kb += 2) {
-            ld1(kb + 1, 1);
-            mm(0);
-            __builtin_amdgcn_sched_barrier(0);
-            if (kb + 2 <= kb1_hi) ld1(kb + 2, 0);
-            mm(1);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        if (kb <= kb1_hi) mm(0);
-        // X K2^T: K2[c][k] = t2[c - k + NK]
-        const T* pa2 = X + r * LD + lk;
-        const T* pb2 = t2 + li + NK - lk;
-        if (band >= NK - 1) {
-            // dense symbols: every (k-step, column block) pair, no tests
-            auto ld2 = [&](int k, int buf) {
-                a[buf] = pa2[4 * k];
-#pragma unroll
-                for (int cb = 0; cb < NW; ++cb) b[buf][cb] = pb2[16 * cb - 4 * k];
-            };
-            ld2(0, 0);
-            for (int k = 0; k < NK / 4; k += 2) {
-                ld2(k + 1, 1);
-                mm(0);
-                __builtin_amdgcn_sched_barrier(0);
-                if (k + 2 < NK / 4) ld2(k + 2, 0);
-                mm(1);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        } else {
-#pragma unroll 2
-            for (int k = 0; k < NK / 4; ++k) {
-                const T a2 = pa2[4 * k];
-#pragma unroll
-                for (int cb = 0; cb < NW; ++cb) {
-                    if (4 * k + 3 < 16 * cb - band || 4 * k > 16 * cb + 15 + band) continue;
-                    acc[cb] = mma(a2, pb2[16 * cb - 4 * k], acc[cb]);
-                }
-            }
-        }
-    };
+    auto single = [&](V (&acc)[NW]) { single_products<T, NK>(acc, X, t1, t2, w, li, lk, band); };
     // sacc = Theta_12 X on the skewed tiles, then scattered into X once every
     // wave is done reading it
     auto pair_to_lds = [&](V (&sacc)[NS]) {
         if constexpr (TWO) {
 #pragma unroll
             for (int j = 0; j < NS; ++j) sacc[j] = V{0, 0, 0, 0};
-            // over the k-block offset d = KB - w: the A operand depends on d
-            // alone and the tiles j meeting k-block KB = w + d are
-            // j in [max(0, d), min(NW, d + NW)], fixed per d; operands of the
-            // next k-step read during the current one
-            const T* pa0 = tk + li + NK - lk;
-            const T* pb0 = X + lk * (LD - 1) + 16 * w * LD + li;
-            T a[2], bv[2][NS];
-#pragma unroll
-            for (int d = -(NW - 1); d <= NW - 1; ++d) {
-                if (w + d < 0 || w + d >= NW) continue;  // wave-uniform
-                const int lo = d < 0 ? 0 : d, hi = d < 0 ? d + NW : NW;
-                auto ldp = [&](int i, int buf) {
-                    a[buf] = pa0[-16 * d - 4 * i];
-                    const T* pb = pb0 + (16 * d + 4 * i) * (LD - 1);
-#pragma unroll
-                    for (int j = 0; j < NS; ++j)
-                        if (j >= lo && j <= hi) bv[buf][j] = pb[16 * j];
-                };
-                ldp(0, 0);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int cur = i & 1;
-                    if (i + 1 < 4) ldp(i + 1, cur ^ 1);
-#pragma unroll
-                    for (int j = 0; j < NS; ++j)
-                        if (j >= lo && j <= hi) sacc[j] = mma(a[cur], bv[cur][j], sacc[j]);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
+            pair_products<T, NK>(sacc, X, tk, w, li, lk);
         }
         __syncthreads();  // every wave is done reading the plane
         if constexpr (TWO) {
@@ -530,7 +558,7 @@ __global__ __launch_bounds__(NK / 16 * 64 * planes_per_block<NK>()) void k_theta
     const long pl = (long)blockIdx.x * planes_per_block<NK>() + g;
     PlaneJob<T> J{u, vin, out, pl, nx, sig1, sig2, kap, ksem, ksem2, band, tau};
     T* smem = reinterpret_cast<T*>(smem_raw) + (size_t)g * (Plane<T, NK>::bytes / sizeof(T));
-    theta_plane<T, NK, TWO, SEM, MODE>(J, smem, threadIdx.x % NT, pl < np);
+    theta_plane<T, NK, TWO, SEM, MODE, (NT * planes_per_block<NK>() <= 512)>(J, smem, threadIdx.x % NT, pl < np);
 }
 
 
@@ -540,7 +568,7 @@ __global__ __launch_bounds__(NK / 16 * 64 * planes_per_block<NK>()) void k_theta
 // waves run the same plane-size template; up to BLK/(64 NK/16) planes of the
 // item share the workgroup, one LDS slice each.
 // ---------------------------------------------------------------------------
-template <typename T, int NK, int MODE>
+template <typename T, int NK, int PB, int MODE>
 __device__ __forceinline__ void theta_batch_item(const T* u_pool, const T* v_pool, T* out_pool,
                                                  const BatchInst& I, const ThItem& item,
                                                  const double* sig_pool, const double* kap_pool,
@@ -554,9 +582,9 @@ __device__ __forceinline__ void theta_batch_item(const T* u_pool, const T* v_poo
                   kap_pool + I.tab_off, nullptr, nullptr, I.band, I.tau};
     T* slice = smem + (size_t)(active ? g : 0) * (Plane<T, NK>::bytes / sizeof(T));
     if (I.two_body)
-        theta_plane<T, NK, true, false, MODE>(J, slice, threadIdx.x % NT, active);
+        theta_plane<T, NK, true, false, MODE, false>(J, slice, threadIdx.x % NT, active);
     else
-        theta_plane<T, NK, false, false, MODE>(J, slice, threadIdx.x % NT, active);
+        theta_plane<T, NK, false, false, MODE, false>(J, slice, threadIdx.x % NT, active);
 }
 
 template <typename T, int NK, int PB, int MODE>
@@ -570,7 +598,7 @@ __global__ __launch_bounds__(NK / 16 * 64 * PB) void k_theta_batch(
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const ThItem item = items[it];
         const BatchInst I = insts[item.inst];
-        theta_batch_item<T, NK, MODE>(u_pool, v_pool, out_pool, I, item, sig_pool, kap_pool, smem);
+        theta_batch_item<T, NK, PB, MODE>(u_pool, v_pool, out_pool, I, item, sig_pool, kap_pool, smem);
     }
 }
 
