@@ -59,9 +59,21 @@ __device__ inline void split_pair2(float x0, float x1, unsigned& p0, unsigned& p
     p0 = __builtin_amdgcn_perm(l, h, 0x05040100u);
     p1 = __builtin_amdgcn_perm(l, h, 0x07060302u);
 }
+// hi + lo of a packed (hi, lo) word as one bf16 dot product with (1, 1): both
+// products are exact and hi + lo is representable in FP32, so this is the
+// exact sum (up to the sign of a zero), one instruction instead of shift,
+// mask and add
 __device__ inline float pair_val(unsigned p)
 {
-    return __uint_as_float(p << 16) + __uint_as_float(p & 0xFFFF0000u);
+    const b2v one = {(__bf16)1.0f, (__bf16)1.0f};
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(b2v, p), one, 0.0f, false);
+}
+// (a.hi + a.lo) - (b.hi + b.lo) as two dot products: the first is exact, the
+// second rounds the exact difference once
+__device__ inline float pair_diff(unsigned a, unsigned b)
+{
+    const b2v neg = {(__bf16)-1.0f, (__bf16)-1.0f};
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(b2v, b), neg, pair_val(a), false);
 }
 
 template <int NK>
@@ -219,8 +231,8 @@ __global__ __launch_bounds__(NK / 16 * 64) void k_theta_stream_bf16(
                 const unsigned* hi1 = H + Hat(s + m, b + m);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const float d1 = pair_val(lo1[q]) - pair_val(hi1[q]);
-                    const float d2 = pair_val(lo2[q]) - pair_val(hi2[q]);
+                    const float d1 = pair_diff(lo1[q], hi1[q]);
+                    const float d2 = pair_diff(lo2[q], hi2[q]);
                     acc[j][q] += s1 * d1 + s2 * d2;
                 }
                 __builtin_amdgcn_sched_barrier(0);
