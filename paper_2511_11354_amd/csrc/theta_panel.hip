@@ -109,18 +109,26 @@ __global__ __launch_bounds__((PanelLayout<T, NK>::NT)) void k_theta_panel(const 
     const int kb = tid / (NC / BE), cbf = (tid % (NC / BE)) * BE;   // F row panel
     const int ck = tid / (KP / BE), kq = (tid % (KP / BE)) * BE;    // K2 panel
     T ak[AE], af[AE], bf[BE], bk[BE];
-    auto fetch = [&](int p) {
-        const int k0 = p * KP;
+    // per-thread operand pointers, advanced by one panel per fetch
+    const T* pk1 = K1 + (long)ra * NK + ka;
+    const T* pf = F + (long)ra * NK + ka;
+    const T* pbf = F + (long)kb * NK + c0 + cbf;
+    const T* pk2 = K2 + (long)(c0 + ck) * NK + kq;
+    auto fetch = [&](int) {
 #pragma unroll
         for (int e = 0; e < AE; ++e) {
-            ak[e] = K1[(long)ra * NK + k0 + ka + e];
-            af[e] = F[(long)ra * NK + k0 + ka + e];
+            ak[e] = pk1[e];
+            af[e] = pf[e];
         }
 #pragma unroll
         for (int e = 0; e < BE; ++e) {
-            bf[e] = F[(long)(k0 + kb) * NK + c0 + cbf + e];
-            bk[e] = K2[(long)(c0 + ck) * NK + k0 + kq + e];
+            bf[e] = pbf[e];
+            bk[e] = pk2[e];
         }
+        pk1 += KP;
+        pf += KP;
+        pbf += (long)KP * NK;
+        pk2 += KP;
     };
     auto stage = [&]() {
 #pragma unroll
