@@ -37,7 +37,43 @@ __global__ __launch_bounds__(256) void k_plane_moments(const T* __restrict__ f, 
     const T* F = f + pl * (long)nk * nk;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double a0 = 0.0, ak = 0.0, a2 = 0.0;
-    if (!rows) {
+    if (!rows && 256 % (nk / 2) == 0) {
+        // no per-row sums wanted, and nk / 2 divides the 256 threads: each
+        // thread always reads the same pair of columns n2, n2 + 1 (one
+        // vector) and accumulates over its rows the row-weighted sums
+        //   r0 = sum w1 v,  rk = sum w1 p1^2 v,  r2 = sum w1 v^2,
+        // the column weights entering once at the end
+        typedef T T2 __attribute__((ext_vector_type(2)));
+        const T2* F2 = reinterpret_cast<const T2*>(F);
+        const int hk = nk / 2, half = nk * nk / 2;
+        const int n2 = 2 * ((int)threadIdx.x % hk);
+        const int rstep = 256 / hk;
+        double r0[2] = {0.0, 0.0}, rk[2] = {0.0, 0.0}, r2[2] = {0.0, 0.0};
+        int n1 = (int)threadIdx.x / hk;
+#pragma unroll 4
+        for (int e = threadIdx.x; e < half; e += 256, n1 += rstep) {
+            const T2 v2 = F2[e];
+            const double w1 = w[n1], wp1 = w1 * p[n1] * p[n1];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double v = (double)v2[h];
+                const double t = w1 * v;
+                r0[h] += t;
+                rk[h] += wp1 * v;
+                r2[h] += t * v;
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double w2 = w[n2 + h], pp2 = p[n2 + h] * p[n2 + h];
+            a0 += w2 * r0[h];
+            ak += w2 * (rk[h] + pp2 * r0[h]) * inv2m;
+            a2 += w2 * r2[h];
+        }
+        a0 = wave_sum(a0);
+        ak = wave_sum(ak);
+        a2 = wave_sum(a2);
+    } else if (!rows) {
         // no per-row sums wanted: every moment is a weighted sum of the
         // thread's own terms (pairs of neighbours in n2, read as one vector),
         // reduced once per wave at the end
