@@ -246,7 +246,9 @@ int wig2_band(const wig2_ctx* ctx);
 
 /* Theta kernel selection.  WIG2_THETA_GENERAL: one plane per workgroup,
  * single-body products on the matrix cores over the symbol's band (any band,
- * box SEM matrices, bf16x2).  WIG2_THETA_STREAM: persistent workgroups that
+ * box SEM matrices, bf16x2); on the torus at nk = 32 .. 128 its Strang Heun
+ * step runs in one pass per plane as well (FP64 / FP32; the potentials
+ * frozen over the step).  WIG2_THETA_STREAM: persistent workgroups that
  * prefetch the next plane while the matrix cores contract the pair term of
  * the current one; single-body differences on the vector ALUs; needs a
  * torus, FP64 or FP32, nk in {32, 48, 64, 96, 128} and a single-body band of
@@ -255,8 +257,8 @@ int wig2_band(const wig2_ctx* ctx);
  * kernels' f + (dt/2)(Theta f + Theta g) up to rounding; with the Strang
  * scheme both Heun stages run in one pass per plane (f read and f' written
  * once; the plane stays in LDS between the two applications of Theta).
- * WIG2_THETA_AUTO (default): the streaming kernel where it applies and is
- * the faster one on MI355X (FP64: nk in {32, 64, 96, 128}; FP32: nk = 128).
+ * WIG2_THETA_AUTO (default): the streaming kernel wherever it applies (it
+ * is the faster one on MI355X at every plane size it supports).
  * wig2_set_theta_path returns WIG2_ENOTSUP for STREAM when the current
  * potentials rule it out (the choice then stays unchanged); with AUTO or
  * STREAM, potentials set later that rule it out select GENERAL.

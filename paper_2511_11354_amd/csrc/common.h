@@ -93,7 +93,8 @@ struct ThetaArgs {
 template <typename T>
 hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, double tau,
                         hipStream_t st);
-// One-pass Heun step of the general kernel (torus, FP64 / FP32):
+// One-pass Heun step of the general kernel (torus, nk = 32 .. 128, FP64 /
+// FP32; theta_heun_general_ok tells where it applies):
 // out = x + (tau/2)(Theta x + Theta (x + tau Theta x)); out may alias x.
 bool theta_heun_general_ok(const ThetaArgs& a);
 template <typename T>

@@ -380,9 +380,9 @@ __device__ __forceinline__ void theta_plane(const PlaneJob<T>& J, T* smem, int t
 }
 
 // ---------------------------------------------------------------------------
-// One-pass Heun step on the general kernel (torus, any supported nk, dense
-// or banded single-body symbols): out = f + (tau/2)(Theta f + Theta g), g = f + tau
-// Theta f, with the potentials frozen over the step (Strang's sub-step), in
+// One-pass Heun step on the general kernel (torus, nk = 32 .. 128, dense or
+// banded single-body symbols): out = f + (tau/2)(Theta f + Theta g), g = f +
+// tau Theta f, with the potentials frozen over the step (Strang's sub-step), in
 // one pass over the plane instead of the two stage launches, which read the
 // state four times and write it twice.  Theta acts within the plane, so the
 // plane stays in LDS between the two applications:
