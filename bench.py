@@ -39,11 +39,24 @@ def theta_flops_per_point(nk: int, band: int) -> float:
     return 2.0 * (2.0 * m1 + m12)
 
 
-def kernel_model(name, npts, elem, nk, band, precision, dense=False, pair=False):
+def fft_flops_per_point(nk):
+    """Theta by 2-D FFT convolution of a plane zero-padded to N = 2 nk: nk/2
+    forward and nk/2 inverse row transforms (two real rows per complex
+    transform), a forward and an inverse transform for each of the N/2 + 1
+    column frequencies, 5 N log2 N flops per complex transform of length N,
+    and the multiply by the purely imaginary symbol (2 flops per complex
+    value), per plane point."""
+    n = 2 * nk
+    per_plane = (nk + 2 * (n // 2 + 1)) * 5.0 * n * math.log2(n) + (n // 2 + 1) * 2.0 * n
+    return per_plane / (nk * nk)
+
+
+def kernel_model(name, npts, elem, nk, band, precision, dense=False, pair=False, fft=False):
     """Algorithmic (bytes, flops) of one launch of a kernel class.  dense: the
     box's SEM operator, two dense nk x nk products per plane (4 nk flops/pt);
     pair: the box's two-body SEM operator, four products per plane through
-    the y-lattice (24 nk flops/pt), part of every Theta application."""
+    the y-lattice (24 nk flops/pt), part of every Theta application; fft:
+    Theta by the FFT convolution (fft_flops_per_point)."""
     if name == "advect_x1x1":
         return 2 * elem * npts, 40.0 * npts  # two sweeps, one read and one write
     if name.startswith("advect"):
@@ -55,6 +68,8 @@ def kernel_model(name, npts, elem, nk, band, precision, dense=False, pair=False)
         # nx^2 nk^2 = npts terms of 7 flops (Im(E Q), two multiply-adds)
         return elem * npts, 4.0 * npts + 7.0 * npts
     fl = (4.0 * nk if dense else theta_flops_per_point(nk, band)) * npts
+    if fft:
+        fl = fft_flops_per_point(nk) * npts
     if pair:
         fl += 24.0 * nk * npts
     if name == "theta_stage1":
@@ -453,10 +468,13 @@ def main():
                     help="V_ext of the box workload")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"),
                     help="autotuner cache for the ensemble workload (runtime output, untracked)")
-    ap.add_argument("--forms", default="fp32,bf16x2,hartree",
+    ap.add_argument("--forms", default="fp32,bf16x2,hartree,fft",
                     help="extra legs of the default 128^4 line, comma separated: fp32, bf16x2 "
-                         "(same workload and steps, errors against the FP64 run's final state) "
-                         "and hartree (FP64 with the mean field lambda = 1); empty for none")
+                         "(same workload and steps, errors against the FP64 run's final state), "
+                         "hartree (FP64 with the mean field lambda = 1) and fft (FP64, Theta by "
+                         "the FFT convolution instead of the direct products); empty for none")
+    ap.add_argument("--theta-path", default="auto", choices=["auto", "general", "stream", "fft"],
+                    help="Theta kernel of the main leg (torus workloads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run plain device copies of the state size (for counter scaling)")
@@ -504,6 +522,7 @@ def main():
     forms = [f for f in a.forms.split(",") if f] if (a.workload == "large" and a.precision == "fp64") else []
     main_leg = run_form(w, f0, box, a.scheme, a.precision, a.steps, a.warmup,
                         lam=1.0 if a.workload == "box-meanfield" else 0.0, keep_state=bool(forms),
+                        theta_path=None if box or a.theta_path == "auto" else a.theta_path,
                         copy_calibration=a.copy_calibration,
                         gpu_samples=not a.no_cpu and a.workload == "large" and a.precision == "fp64")
     cpu = None
@@ -515,8 +534,9 @@ def main():
     ref_obs = main_leg.pop("obs")
     legs = {}
     for form in forms:
-        prec, lam = ("fp64", 1.0) if form == "hartree" else (form, 0.0)
-        leg = run_form(w, f0, box, a.scheme, prec, a.steps, a.warmup, lam=lam, keep_state=lam == 0.0)
+        prec, lam = ("fp64", 1.0) if form == "hartree" else ("fp64", 0.0) if form == "fft" else (form, 0.0)
+        leg = run_form(w, f0, box, a.scheme, prec, a.steps, a.warmup, lam=lam, keep_state=lam == 0.0,
+                       theta_path="fft" if form == "fft" else None)
         ob = leg.pop("obs")
         st = leg.pop("state", None)
         if st is not None:
@@ -586,13 +606,15 @@ def state_errors(f, r):
 
 
 def run_form(w, f0, box, scheme, precision, steps, warmup, lam=0.0, keep_state=False,
-             copy_calibration=False, gpu_samples=False):
+             copy_calibration=False, gpu_samples=False, theta_path=None):
     """One form of the workload: warm-up, then `steps` timed steps with the
     per-kernel-class HIP event timing on the context stream."""
     import torch
 
     s = make_solver(w, box, scheme, precision, lam)
     s.set_potentials(w.vext, w.v12)
+    if theta_path:
+        s.set_theta_path(theta_path)
     s.set_state(f0)
     band = s.band()
     res = {}
@@ -631,11 +653,13 @@ def run_form(w, f0, box, scheme, precision, steps, warmup, lam=0.0, keep_state=F
     elem = 8 if precision == "fp64" else 4
     dense_band = w.nk - 1 if (lam != 0.0 or "hartree" in w.extra) else band
     pair = box and w.v12 is not None
+    path = s.theta_path()
+    fft = path == "fft"
     kernels = {}
     for name, (ms, cnt) in prof.items():
         if cnt == 0:
             continue
-        by, fl = kernel_model(name, npts, elem, w.nk, dense_band, precision, dense=box, pair=pair)
+        by, fl = kernel_model(name, npts, elem, w.nk, dense_band, precision, dense=box, pair=pair, fft=fft)
         avg = ms / cnt / 1e3
         kernels[name] = {"avg_ms": ms / cnt, "launches": cnt, "GB/s": by / avg / 1e9,
                          "TFLOP/s": fl / avg / 1e12}
@@ -643,18 +667,21 @@ def run_form(w, f0, box, scheme, precision, steps, warmup, lam=0.0, keep_state=F
     # kernel class whenever it runs
     dom = "pair_sem" if prof.get("pair_sem", (0, 0))[1] else max(prof, key=lambda k: prof[k][0])
     ms, cnt = prof[dom]
-    by, fl = kernel_model(dom, npts, elem, w.nk, dense_band, precision, dense=box, pair=pair)
+    by, fl = kernel_model(dom, npts, elem, w.nk, dense_band, precision, dense=box, pair=pair, fft=fft)
     avg = ms / cnt / 1e3
     pk_fl = PEAK["fp64" if precision == "fp64" else ("fp32" if precision == "fp32" else "bf16")]
     t_hbm = by / (PEAK["hbm_gbs"] * 1e9)
     t_fl = fl / (pk_fl * 1e12)
-    if (dom.startswith("theta") or dom == "pair_sem") and t_fl > t_hbm:
+    if fft and dom.startswith("theta"):
+        # the transforms run on the vector ALUs; FP64 / FP32 vector peaks
+        # equal the dense matrix peaks used above (78.6 / 157.3 TFLOP/s)
+        roof = {"bound": "alu", "achieved": fl / avg / 1e12, "peak": pk_fl, "unit": "TFLOP/s"}
+    elif (dom.startswith("theta") or dom == "pair_sem") and t_fl > t_hbm:
         roof = {"bound": "mfma", "achieved": fl / avg / 1e12, "peak": pk_fl, "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": by / avg / 1e9, "peak": PEAK["hbm_gbs"], "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    path = s.theta_path()
-    theta_file = ("theta_panel.hip" if path == "panel" else
+    theta_file = ("theta_fft.hip" if fft else "theta_panel.hip" if path == "panel" else
                   "theta_stream.hip" if path == "stream" else "theta.hip")
     kfile = os.path.join("paper_2511_11354_amd", "csrc",
                          "theta12_sem.hip" if dom == "pair_sem" else

@@ -265,8 +265,18 @@ int wig2_band(const wig2_ctx* ctx);
  * wig2_theta_path returns the kernel the next step uses (>= 0), or
  * WIG2_ESTATE before wig2_set_potentials.  WIG2_THETA_PANEL (reported only):
  * box contexts with nk = 256 always use the panel kernel, which stages the
- * dense SEM products through LDS in k panels. */
-enum { WIG2_THETA_AUTO = 0, WIG2_THETA_GENERAL = 1, WIG2_THETA_STREAM = 2, WIG2_THETA_PANEL = 3 };
+ * dense SEM products through LDS in k panels.  WIG2_THETA_FFT (chosen only
+ * when asked for): the FFT-accelerated route of the two-body cost statement
+ * (Sec. 3.1.2).  On each momentum plane the row, column and anti-diagonal
+ * pseudo-differences form one 2-D linear convolution with an odd kernel.  It
+ * is evaluated as IFFT2(W . FFT2(f)) on the plane zero-padded to
+ * N = 2 nk points per direction, W(k1, k2) = -2i [S1(k1) + S2(k2) +
+ * K(k1 - k2)], S(k) = sum_m s_m sin(2 pi k m / N).  The result equals the
+ * direct sums up to rounding, for any single-body band (mean field
+ * included).  Needs a torus, nk in {32, 64, 128} and FP64 or FP32 (else
+ * WIG2_ENOTSUP).  Heun runs as its two stages.  On MI355X it is slower than
+ * the direct products at every one of these sizes. */
+enum { WIG2_THETA_AUTO = 0, WIG2_THETA_GENERAL = 1, WIG2_THETA_STREAM = 2, WIG2_THETA_PANEL = 3, WIG2_THETA_FFT = 4 };
 int wig2_set_theta_path(wig2_ctx* ctx, int32_t path);
 int wig2_theta_path(const wig2_ctx* ctx);
 

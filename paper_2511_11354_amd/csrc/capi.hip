@@ -65,6 +65,7 @@ struct wig2_ctx {
     void* work = nullptr;  // lazily allocated advection scratch
     double *p_d = nullptr, *w_d = nullptr, *thomas_d = nullptr;
     double *sig_ext_d = nullptr, *sig1_d = nullptr, *sig2_d = nullptr, *kap_d = nullptr;
+    double* fft_sym_d = nullptr;  // FFT Theta path: plane symbols, 3 nx (2 nk)
     double *ksem_d = nullptr, *v12pair_d = nullptr, *sintab_d = nullptr;
     int hartree = WIG2_HARTREE_PAIR;
     double* hart_d = nullptr;  // [nx][nx] Hartree kernel of the mean field
@@ -265,6 +266,7 @@ ThetaArgs theta_args(wig2_ctx* c)
     a.kap = (c->two_body && !c->no_pair) ? c->kap_d : nullptr;
     a.ksem = c->g.periodic ? nullptr : c->ksem_d;
     a.precision = c->prm.precision;
+    a.fft_sym = c->fft_sym_d;
     a.ksem_t = nullptr;
     if (!c->g.periodic && c->g.nk == kPanelThetaNk)
         a.ksem_t = c->elem == 8 ? (const void*)c->ksem_d : (const void*)c->ksem_f;
@@ -318,17 +320,20 @@ hipError_t with_pair_sem(wig2_ctx* c, const T* u, const T* v, double beta, doubl
     return launch_sem12_add<T>(dst, out, c->npts, c->ncu, c->st);
 }
 
+bool use_fft(const wig2_ctx* c) { return c->theta_path == WIG2_THETA_FFT; }
+
 // mode 0: out = Theta u; mode 1: out = u + tau/2 (v + Theta (u + tau v))
 template <typename T>
 hipError_t theta(wig2_ctx* c, const T* u, const T* v, T* out, int mode, double tau)
 {
+    if (use_fft(c)) return launch_theta_fft<T>(theta_args(c), u, v, out, mode, tau, c->st);
     return with_pair_sem<T>(c, u, mode == 1 ? v : nullptr, mode == 1 ? tau : 0.0, mode == 1 ? 0.5 * tau : 1.0, out,
                             [&] { return launch_theta<T>(theta_args(c), u, v, out, mode, tau, c->st); });
 }
 
 bool use_stream(wig2_ctx* c)
 {
-    if (c->theta_path == WIG2_THETA_GENERAL || !theta_stream_ok(theta_args(c))) return false;
+    if (c->theta_path == WIG2_THETA_GENERAL || use_fft(c) || !theta_stream_ok(theta_args(c))) return false;
     if (c->prm.precision == WIG2_BF16X2) return true;  // split-BF16 streaming kernel
     return c->theta_path == WIG2_THETA_STREAM || theta_stream_preferred(c->g.nk, c->elem);
 }
@@ -451,8 +456,8 @@ hipError_t heun_theta(wig2_ctx* c, T* x, T* out)
         return THS(k1, x, out, 2);
     }
     // general kernel: the whole Heun step in one pass where it has that form
-    // (torus), else its two stages
-    if (theta_heun_general_ok(theta_args(c)))
+    // (torus), else its two stages (also the FFT path's form)
+    if (!use_fft(c) && theta_heun_general_ok(theta_args(c)))
         return timed(c, WIG2_PROF_THETA_HEUN,
                      [&] { return launch_theta_heun<T>(theta_args(c), x, out, tau, c->st); });
     if ((e = TH(x, nullptr, k1, 0)) != hipSuccess) return e;
@@ -951,6 +956,8 @@ int wig2_create(const wig2_grid* grid, const wig2_params* prm, void* hip_stream,
         dev_alloc(c, &c->s2_d, np) || dev_alloc(c, &c->rows_d, np * nk) ||
         dev_alloc(c, &c->f1_d, (size_t)nx * nk))
         return bail(WIG2_ENOMEM);
+    if (G.periodic && nk <= kMaxThetaNk && dev_alloc(c, &c->fft_sym_d, (size_t)3 * nx * 2 * nk))
+        return bail(WIG2_ENOMEM);
     if (!G.periodic && dev_alloc(c, &c->ksem_d, (size_t)nx * nk * nk)) return bail(WIG2_ENOMEM);
     if (panel && c->elem == 4 && dev_alloc(c, &c->ksem_f, (size_t)nx * nk * nk)) return bail(WIG2_ENOMEM);
     if (!G.periodic && c->meanfield) {
@@ -997,7 +1004,7 @@ void wig2_destroy(wig2_ctx* c)
                     c->semE_d, c->semQ_d, c->v12pair_d, c->hart_d, c->sintab_d,
                     c->mf_dens_d, c->mf_veff_d, c->s0_d, c->s0b_d, c->skin_d, c->s2_d, c->rows_d,
                     c->f1_d, c->ft, c->fs, c->sur_buf, c->s12_wa, c->s12_wb, c->s12_wc, c->s12_wd,
-                    c->s12_dt, c->s12_wr, c->s12_wh, c->s12_acc};
+                    c->s12_dt, c->s12_wr, c->s12_wh, c->s12_acc, c->fft_sym_d};
     for (void* b : bufs)
         if (b) hipFree(b);
     for (auto& pe : c->prof_ev) {
@@ -1342,7 +1349,9 @@ int wig2_set_sweep_fusion(wig2_ctx* c, int32_t enable)
 
 int wig2_set_theta_path(wig2_ctx* c, int32_t path)
 {
-    if (!c || path < WIG2_THETA_AUTO || path > WIG2_THETA_STREAM) return WIG2_EINVAL;
+    if (!c || path < WIG2_THETA_AUTO || path > WIG2_THETA_FFT || path == WIG2_THETA_PANEL) return WIG2_EINVAL;
+    if (path == WIG2_THETA_FFT && (!c->fft_sym_d || !theta_fft_ok(theta_args(c))))
+        return fail(c, WIG2_ENOTSUP, "FFT Theta needs a torus, nk in {32,64,128} and FP64 or FP32");
     if (path == WIG2_THETA_STREAM && c->has_pot && !theta_stream_ok(theta_args(c)))
         return fail(c, WIG2_ENOTSUP, "streaming Theta needs a torus, nk in {32,48,64,96,128} (BF16X2: "
                                      "{32,64,96,128}) and a single-body band of at most 4 modes");
@@ -1356,6 +1365,7 @@ int wig2_theta_path(const wig2_ctx* c)
     if (!c->has_pot) return WIG2_ESTATE;
     wig2_ctx* m = const_cast<wig2_ctx*>(c);
     if (theta_panel_ok(theta_args(m))) return WIG2_THETA_PANEL;
+    if (use_fft(m)) return WIG2_THETA_FFT;
     return use_stream(m) ? WIG2_THETA_STREAM : WIG2_THETA_GENERAL;
 }
 

@@ -89,6 +89,8 @@ struct ThetaArgs {
     // ksem / ksem_t); NULL: both particles use ksem / ksem_t
     const double* ksem2 = nullptr;
     const void* ksem2_t = nullptr;
+    // FFT path: device workspace of 3 nx (2 nk) doubles for the plane symbols
+    double* fft_sym = nullptr;
 };
 template <typename T>
 hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, double tau,
@@ -99,6 +101,14 @@ hipError_t launch_theta(const ThetaArgs& a, const T* u, const T* v, T* out, int 
 bool theta_heun_general_ok(const ThetaArgs& a);
 template <typename T>
 hipError_t launch_theta_heun(const ThetaArgs& a, const T* x, T* out, double tau, hipStream_t st);
+
+// Theta by 2-D FFT convolution of each momentum plane (theta_fft.hip):
+// torus, nk in {32, 64, 128}, FP64 / FP32, any single-body band.  Same modes
+// as launch_theta (0: out = Theta u; 1: out = u + tau/2 (v + Theta (u + tau v))).
+bool theta_fft_ok(const ThetaArgs& a);
+template <typename T>
+hipError_t launch_theta_fft(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, double tau,
+                            hipStream_t st);
 
 // Box two-body operator (theta12_sem.hip).  Tables in the state's element
 // type: wa (nk x 2nk), wb (2nk x 2nk), wc (2nk x 2nk), wd (2nk x nk), dtab

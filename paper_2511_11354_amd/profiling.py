@@ -50,6 +50,10 @@ def kernel_class(name: str):
         return cls, os.path.join(CSRC, "theta_panel.hip")
     if n.startswith("k_theta_heun<"):
         return "theta_heun", os.path.join(CSRC, "theta.hip")
+    if n.startswith("k_theta_fft<"):
+        return "theta_fft", os.path.join(CSRC, "theta_fft.hip")
+    if n.startswith("k_fft_symbols"):
+        return "theta_fft_symbols", os.path.join(CSRC, "theta_fft.hip")
     m = re.match(r"k_theta<(\w+), (\d+), (\w+), (\w+), (\d)>", n)
     if m:
         return ("theta_stage1" if m.group(5) == "0" else "theta_stage2"), os.path.join(CSRC, "theta.hip")

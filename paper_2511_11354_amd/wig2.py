@@ -280,18 +280,18 @@ class Solver:
         launch (default) or as two."""
         self._check(self._L.wig2_set_sweep_fusion(self._h, int(bool(enable))), "wig2_set_sweep_fusion")
 
-    THETA_PATHS = {"auto": 0, "general": 1, "stream": 2}
+    THETA_PATHS = {"auto": 0, "general": 1, "stream": 2, "fft": 4}
 
     def set_theta_path(self, path: str):
-        """Theta kernel choice: "auto", "general" or "stream"."""
+        """Theta kernel choice: "auto", "general", "stream" or "fft"."""
         self._check(self._L.wig2_set_theta_path(self._h, self.THETA_PATHS[path]), "wig2_set_theta_path")
 
     def theta_path(self) -> str:
-        """Kernel the next step uses ("general", "stream" or "panel")."""
+        """Kernel the next step uses ("general", "stream", "panel" or "fft")."""
         r = self._L.wig2_theta_path(self._h)
         if r < 0:
             self._check(r, "wig2_theta_path")
-        return {1: "general", 2: "stream", 3: "panel"}[r]
+        return {1: "general", 2: "stream", 3: "panel", 4: "fft"}[r]
 
     def attach_surrogate(self, model, drift_tol=1e-6, exact_check_every=8):
         """Advance whole blocks with the learned pair increment (exact
