@@ -96,6 +96,45 @@ def test_p3_p4_cosine_shift_identities(orc, hbar):
         assert np.abs(a - b).max() <= 5e-14 * np.abs(b).max()
 
 
+def test_fft_route_equals_direct_sums(orc):
+    """The FFT route of the two-body cost statement (Sec. 3.1.2): on each
+    momentum plane the three pseudo-difference sums are one 2-D linear
+    convolution with an odd kernel, so with both momentum indices zero-padded
+    to N = 2 nk, Theta f = Re IFFT2(W . FFT2 f) on the nk x nk window,
+    W(k1, k2) = -2i c [S1(k1) + S2(k2) + K(k1 - k2)],
+    S(k) = sum_{m >= 1} s_m sin(2 pi k m / N), c = 2/hbar.  Computed with
+    numpy's FFT (an independent route) against the oracle's direct sums,
+    with dense symbols so every mode enters; without the padding (cyclic on
+    nk points) the same formula is wrong."""
+    nx, nk, hbar = 3, 16, 0.7
+    g = orc.grid(nx, nk, True, 1, -10.0, 10.0, hbar=hbar)
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal((nx, nx, nk, nk))
+    sig1, sig2 = rng.standard_normal((nx, nk)), rng.standard_normal((nx, nk))
+    vh = rng.standard_normal(nk)
+    ref = orc.theta_periodic(g, sig1, sig2, vh, f, True)
+    m = np.arange(1, nk)
+    c = 2.0 / hbar
+
+    def route(N):
+        sinm = np.sin(2 * np.pi * np.outer(np.arange(N), m) / N)  # [k][m]
+        k = np.arange(N)
+        out = np.zeros_like(f)
+        for i1 in range(nx):
+            for i2 in range(nx):
+                kap = vh[1:] * np.sin(2 * np.pi * m * (i1 - i2) / nx)
+                S1, S2, K = sinm @ sig1[i1, 1:], sinm @ sig2[i2, 1:], sinm @ kap
+                W = -2j * c * (S1[:, None] + S2[None, :] + K[(k[:, None] - k[None, :]) % N])
+                pad = np.zeros((N, N))
+                pad[:nk, :nk] = f[i1, i2]
+                out[i1, i2] = np.fft.ifft2(W * np.fft.fft2(pad)).real[:nk, :nk]
+        return out
+
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(route(2 * nk) - ref)) <= 1e-13 * scale
+    assert np.max(np.abs(route(nk) - ref)) > 1e-2 * scale
+
+
 def test_p6_antisymmetry(orc):
     """Every pseudo-difference operator is skew in p: sum_p f Theta f = 0 per x-pair."""
     g = orc.grid(8, 24, True, 1, -10.0, 10.0)
