@@ -60,8 +60,10 @@ __device__ __forceinline__ cx<T> times_mi(cx<T> a) { return {a.i, -a.r}; }
 // a linear map over GF(2) under which exchanging with l ^ 2^s is exchanging
 // with L ^ m_s, m = (1, 3, 7, 15, 16, 32).  The first four are the DPP lane
 // patterns quad_perm [1,0,3,2], quad_perm [3,2,1,0], row_half_mirror and
-// row_mirror (vector-ALU moves); only xor 16 and xor 32 go through the LDS
-// crossbar (ds_bpermute), whose issue rate bounds this kernel otherwise.
+// row_mirror (vector-ALU moves).  For xor 16 and xor 32 the row and half
+// swaps (v_permlane16_swap, v_permlane32_swap) give every lane both members
+// of its pair.  No exchange goes through the LDS crossbar (ds_bpermute),
+// whose issue rate bounded this kernel.
 __device__ __forceinline__ int logical_lane(int L) { return (L & 0x38) | ((L ^ (L >> 1)) & 7); }
 
 template <int CTRL>
@@ -99,6 +101,55 @@ __device__ __forceinline__ T xchg(T v, int s)
 
 template <typename T>
 __device__ __forceinline__ cx<T> xchg_cx(cx<T> a, int s) { return {xchg(a.r, s), xchg(a.i, s)}; }
+
+// Both members of the pair {L, L ^ 16} (S = 4) or {L, L ^ 32} (S = 5): lo is
+// the value of the lane with the bit clear, hi of the lane with it set.
+// Swapping the odd 16-lane rows (upper halves) of one copy with the even rows
+// (lower halves) of another leaves the lower members in the first copy and
+// the upper members in the second, in every lane.
+template <int S>
+__device__ __forceinline__ void pair_lohi(unsigned v, unsigned& lo, unsigned& hi)
+{
+    if constexpr (S == 4) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        lo = r[0];
+        hi = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        lo = r[0];
+        hi = r[1];
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void pair_lohi(double v, double& lo, double& hi)
+{
+    unsigned l0, h0, l1, h1;
+    pair_lohi<S>((unsigned)__double2loint(v), l0, h0);
+    pair_lohi<S>((unsigned)__double2hiint(v), l1, h1);
+    lo = __hiloint2double((int)l1, (int)l0);
+    hi = __hiloint2double((int)h1, (int)h0);
+}
+
+template <int S>
+__device__ __forceinline__ void pair_lohi(float v, float& lo, float& hi)
+{
+    unsigned l, h;
+    pair_lohi<S>(__float_as_uint(v), l, h);
+    lo = __uint_as_float(l);
+    hi = __uint_as_float(h);
+}
+
+// lo + sgn hi over the pair of stage s >= 4 (the lower lane's sum, the upper
+// lane's difference)
+template <int S, typename T>
+__device__ __forceinline__ cx<T> pair_combine(cx<T> a, T sg)
+{
+    cx<T> lo, hi;
+    pair_lohi<S>(a.r, lo.r, hi.r);
+    pair_lohi<S>(a.i, lo.i, hi.i);
+    return {fma(sg, hi.r, lo.r), fma(sg, hi.i, lo.i)};
+}
 
 // a t (CONJ: a conj(t))
 template <bool CONJ, typename T>
@@ -157,8 +208,13 @@ __device__ __forceinline__ void dif64(cx<T> (&x)[R], const Twiddles<T, R>& w)
         const T sg = w.sgn[s];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const cx<T> y = xchg_cx(x[k], s);
-            const cx<T> d = {fma(sg, x[k].r, y.r), fma(sg, x[k].i, y.i)};
+            cx<T> d;
+            if (s >= 4) {
+                d = s == 4 ? pair_combine<4>(x[k], sg) : pair_combine<5>(x[k], sg);
+            } else {
+                const cx<T> y = xchg_cx(x[k], s);
+                d = {fma(sg, x[k].r, y.r), fma(sg, x[k].i, y.i)};
+            }
             x[k] = s == 0 ? d : cmul<INV>(d, w.stage[s]);
         }
     }
@@ -176,8 +232,12 @@ __device__ __forceinline__ void dit64(cx<T> (&x)[R], const Twiddles<T, R>& w)
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const cx<T> m = s == 0 ? x[k] : cmul<INV>(x[k], w.stage[s]);
-            const cx<T> o = xchg_cx(m, s);
-            x[k] = {fma(sg, m.r, o.r), fma(sg, m.i, o.i)};
+            if (s >= 4) {
+                x[k] = s == 4 ? pair_combine<4>(m, sg) : pair_combine<5>(m, sg);
+            } else {
+                const cx<T> o = xchg_cx(m, s);
+                x[k] = {fma(sg, m.r, o.r), fma(sg, m.i, o.i)};
+            }
         }
     }
 }
