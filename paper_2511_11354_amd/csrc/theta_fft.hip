@@ -24,7 +24,8 @@
 //    two rows.  Both halves add into registers.
 // Each transform has N = 64 R points and is done by one wavefront:
 //  * the in-lane R-point DFT and its twiddles (four-step decomposition);
-//  * a 64-point radix-2 transform across the lanes by xor shuffles.
+//  * a 64-point radix-2 transform across the lanes, by lane exchanges on
+//    the vector ALUs (DPP moves and row / half swaps).
 //  * Decimation in frequency: natural order in, bit-reversed out.
 //  * Decimation in time: bit-reversed order in, natural order out.
 // Lane orders are chosen so that every LDS access of a wave is consecutive.
@@ -62,8 +63,10 @@ __device__ __forceinline__ cx<T> times_mi(cx<T> a) { return {a.i, -a.r}; }
 // patterns quad_perm [1,0,3,2], quad_perm [3,2,1,0], row_half_mirror and
 // row_mirror (vector-ALU moves).  For xor 16 and xor 32 the row and half
 // swaps (v_permlane16_swap, v_permlane32_swap) give every lane both members
-// of its pair.  No exchange goes through the LDS crossbar (ds_bpermute),
-// whose issue rate bounded this kernel.
+// of its pair (SWAP), so no exchange goes through the LDS crossbar, whose
+// issue rate bounds the FP64 kernels at nk >= 64; the FP32 and small-plane
+// variants, with more waves per SIMD and less vector-ALU headroom, keep
+// ds_bpermute for those two stages (measured faster there).
 __device__ __forceinline__ int logical_lane(int L) { return (L & 0x38) | ((L ^ (L >> 1)) & 7); }
 
 template <int CTRL>
@@ -200,7 +203,7 @@ __device__ inline void make_twiddles(Twiddles<T, R>& w, int lane, int blane)
 // 64-point transforms across the lanes, R independent sequences per lane.
 // Decimation in frequency: lane L ends with element br(L).
 // Lower lane: x + y; upper lane: (y - x) t.
-template <bool INV, typename T, int R>
+template <bool INV, bool SWAP, typename T, int R>
 __device__ __forceinline__ void dif64(cx<T> (&x)[R], const Twiddles<T, R>& w)
 {
 #pragma unroll
@@ -209,7 +212,7 @@ __device__ __forceinline__ void dif64(cx<T> (&x)[R], const Twiddles<T, R>& w)
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             cx<T> d;
-            if (s >= 4) {
+            if (SWAP && s >= 4) {
                 d = s == 4 ? pair_combine<4>(x[k], sg) : pair_combine<5>(x[k], sg);
             } else {
                 const cx<T> y = xchg_cx(x[k], s);
@@ -223,7 +226,7 @@ __device__ __forceinline__ void dif64(cx<T> (&x)[R], const Twiddles<T, R>& w)
 // Decimation in time: lane L starts with element br(L), ends with element L.
 // Lower lane: x + t y; upper lane: y - t x (the upper lane's value is
 // multiplied by t before the exchange).
-template <bool INV, typename T, int R>
+template <bool INV, bool SWAP, typename T, int R>
 __device__ __forceinline__ void dit64(cx<T> (&x)[R], const Twiddles<T, R>& w)
 {
 #pragma unroll
@@ -232,7 +235,7 @@ __device__ __forceinline__ void dit64(cx<T> (&x)[R], const Twiddles<T, R>& w)
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const cx<T> m = s == 0 ? x[k] : cmul<INV>(x[k], w.stage[s]);
-            if (s >= 4) {
+            if (SWAP && s >= 4) {
                 x[k] = s == 4 ? pair_combine<4>(m, sg) : pair_combine<5>(m, sg);
             } else {
                 const cx<T> o = xchg_cx(m, s);
@@ -285,6 +288,7 @@ struct FftShape {
     static constexpr int RPW = NK / 2 / NW;     // row pairs per wavefront
     static constexpr int NA = R >= 2 ? R / 2 : 1;  // in-lane positions inside the window
     static constexpr int PITCH = NJ * 64 + 1;   // complex values per row pair in LDS
+    static constexpr bool SWAP = sizeof(T) == 8 && NK >= 64;  // lane swaps for xor 16 / 32
     static constexpr size_t lds() { return sizeof(cx<T>) * (NK / 2) * PITCH + sizeof(T) * 3 * N; }
 };
 
@@ -318,6 +322,7 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
 {
     using S = FftShape<T, NK>;
     constexpr int N = S::N, R = S::R, P = S::P, NJ = S::NJ, RPW = S::RPW, NA = S::NA, PITCH = S::PITCH;
+    constexpr bool SW = S::SWAP;
     extern __shared__ unsigned char smem_raw[];
     cx<T>* A = reinterpret_cast<cx<T>*>(smem_raw);
     T* tab = reinterpret_cast<T*>(A + (NK / 2) * PITCH);  // S1 | S2 | K, N each
@@ -373,7 +378,7 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
             }
             if (q + 1 < RPW) load_rows(r + 1);
             fwd_inlane(x, tw.rev);
-            dit64<false>(x, tw);
+            dit64<false, SW>(x, tw);
 #pragma unroll
             for (int jj = 0; jj < NJ; ++jj) A[r * PITCH + jj * 64 + lane] = x[p + P * jj];
         }
@@ -402,7 +407,7 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
                 }
             }
             fwd_inlane(x, tw.nat);
-            dif64<false>(x, tw);
+            dif64<false, SW>(x, tw);
             const T s2 = S2[k2];
 #pragma unroll
             for (int k1 = 0; k1 < R; ++k1) {
@@ -412,7 +417,7 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
                 x[k1] = times_mi(x[k1]);
                 x[k1] = {x[k1].r * wgt, x[k1].i * wgt};
             }
-            dit64<true>(x, tw);
+            dit64<true, SW>(x, tw);
             inv_inlane(x, tw.nat);
 #pragma unroll
             for (int a = 0; a < NA; ++a) {
@@ -439,7 +444,7 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
             for (int k = 0; k < R; ++k) z[k] = {T(0), T(0)};
 #pragma unroll
             for (int jj = 0; jj < NJ; ++jj) z[p + P * jj] = A[r * PITCH + jj * 64 + lane];
-            dif64<true>(z, tw);
+            dif64<true, SW>(z, tw);
             inv_inlane(z, tw.rev);
 #pragma unroll
             for (int a = 0; a < NA; ++a) acc[q][a] = acc[q][a] + z[a];
