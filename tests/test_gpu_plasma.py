@@ -140,3 +140,22 @@ def test_two_stream_grows():
     assert np.all(np.isfinite(ws))
     assert ws.max() > 1000 * early.min()
     assert ws[ts >= 20.0].min() > 10 * ws[np.argmin(np.abs(ts - 10.0))]
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("scheme", ["strang", "lawson"])
+def test_poisson_steps_fft_path_match_oracle(orc, scheme):
+    """The Wigner-Poisson mean field on the FFT route of Theta (its dense
+    symbols rebuilt per sub-step into the plane spectra)."""
+    nx, nk, dt = 16, 64, 0.01
+    s, w, f0 = solver(nx, nk, "two-stream", True, scheme, False, dt)
+    s.set_theta_path("fft")
+    assert s.theta_path() == "fft"
+    g = orc.grid(nx, nk, True, 1, w.x_min, w.x_max)
+    tb = orc.tables(g, None, w.v12)
+    print(f"poisson fft {scheme}: ", end="", flush=True)
+    s.step(3)
+    ref = orc.step(g, f0, tb, 3, dt, scheme=scheme, lam=w.extra["lam"], two_body=True, hartree="poisson")
+    e = eps_inf(s.get_state(), ref)
+    print(f"3 steps eps_inf {e:.3e}", flush=True)
+    assert e <= 1e-12
