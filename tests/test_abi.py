@@ -77,3 +77,22 @@ def test_null_arguments():
     assert L.wig2_step(None, 1) == wig2.EINVAL
     assert L.wig2_set_state(None, None) == wig2.EINVAL
     L.wig2_destroy(None)
+
+
+def _enum(prefix):
+    txt = open(os.path.join(ROOT, "include", "wig2.h")).read()
+    return {m.group(1): int(m.group(2)) for m in re.finditer(rf"\b({prefix}[A-Z0-9_]+)\s*=\s*(\d+)", txt)}
+
+
+def test_binding_tables_match_header_enums():
+    """The binding's Theta-path names and profile classes carry the values
+    include/wig2.h assigns (the binding holds no values of its own)."""
+    paths = _enum("WIG2_THETA_")
+    assert wig2.Solver.THETA_PATHS == {"auto": paths["WIG2_THETA_AUTO"], "general": paths["WIG2_THETA_GENERAL"],
+                                       "stream": paths["WIG2_THETA_STREAM"], "fft": paths["WIG2_THETA_FFT"]}
+    assert paths["WIG2_THETA_PANEL"] not in wig2.Solver.THETA_PATHS.values()  # reported, never chosen
+    prof = _enum("WIG2_PROF_")
+    n = prof.pop("WIG2_PROF_N")
+    assert len(wig2.PROF_NAMES) == n
+    for name, i in prof.items():
+        assert wig2.PROF_NAMES[i] == name[len("WIG2_PROF_"):].lower()
