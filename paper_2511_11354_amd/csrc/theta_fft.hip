@@ -175,6 +175,9 @@ struct Twiddles {
     T sgn[6];
     cx<T> nat[R];    // e^{-2 pi i lane k1 / N}, k1 < R
     cx<T> rev[R];    // e^{-2 pi i br(lane) k1 / N}
+    // the register-transposed stages (every lane): e^{-i pi (lane mod 16) / 16},
+    // e^{-i pi (lane mod 32) / 32} and e^{-i pi (lane mod 16) / 32}
+    cx<T> t4, t5, t5lo;
 };
 
 template <typename T, int R>
@@ -198,16 +201,23 @@ __device__ inline void make_twiddles(Twiddles<T, R>& w, int lane, int blane)
         sincospi(-2.0 * ((blane * k) % N) / N, &sn, &cs);
         w.rev[k] = {(T)cs, (T)sn};
     }
+    double sn, cs;
+    sincospi(-(double)(lane & 15) / 16, &sn, &cs);
+    w.t4 = {(T)cs, (T)sn};
+    sincospi(-(double)(lane & 31) / 32, &sn, &cs);
+    w.t5 = {(T)cs, (T)sn};
+    sincospi(-(double)(lane & 15) / 32, &sn, &cs);
+    w.t5lo = {(T)cs, (T)sn};
 }
 
 // 64-point transforms across the lanes, R independent sequences per lane.
 // Decimation in frequency: lane L ends with element br(L).
 // Lower lane: x + y; upper lane: (y - x) t.
-template <bool INV, bool SWAP, typename T, int R>
+template <bool INV, bool SWAP, typename T, int R, int SHI = 5>
 __device__ __forceinline__ void dif64(cx<T> (&x)[R], const Twiddles<T, R>& w)
 {
 #pragma unroll
-    for (int s = 5; s >= 0; --s) {
+    for (int s = SHI; s >= 0; --s) {
         const T sg = w.sgn[s];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -226,11 +236,11 @@ __device__ __forceinline__ void dif64(cx<T> (&x)[R], const Twiddles<T, R>& w)
 // Decimation in time: lane L starts with element br(L), ends with element L.
 // Lower lane: x + t y; upper lane: y - t x (the upper lane's value is
 // multiplied by t before the exchange).
-template <bool INV, bool SWAP, typename T, int R>
+template <bool INV, bool SWAP, typename T, int R, int SEND = 6>
 __device__ __forceinline__ void dit64(cx<T> (&x)[R], const Twiddles<T, R>& w)
 {
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
+    for (int s = 0; s < SEND; ++s) {
         const T sg = w.sgn[s];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -278,6 +288,141 @@ __device__ __forceinline__ void inv_inlane(cx<T> (&z)[R], const cx<T> (&tw)[R])
     }
 }
 
+// Register-transposed stages for four sequences per lane (R = 4).  A row
+// swap of registers a and b (v_permlane16_swap for lane bit 4, S = 4, or
+// v_permlane32_swap for lane bit 5, S = 5) leaves in every lane both members
+// of a pair of lanes: a holds the lower member (bit clear), b the upper.
+// The sequence they belong to is now given by the lane bit, and the
+// butterfly runs in registers with a useful twiddle in every lane.  A
+// transform whose last two stages are done this way ends "transposed": slot k
+// holds positions with bit 4 = k >> 1 and bit 5 = k & 1, and lane bits 5, 4
+// give the in-lane index k1 = bit5 | bit4 << 1.  swap_rows moves a slot bit
+// back into its lane bit.
+template <int S>
+__device__ __forceinline__ void swap_rows(unsigned& a, unsigned& b)
+{
+    if constexpr (S == 4) {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void swap_rows(double& a, double& b)
+{
+    unsigned al = (unsigned)__double2loint(a), ah = (unsigned)__double2hiint(a);
+    unsigned bl = (unsigned)__double2loint(b), bh = (unsigned)__double2hiint(b);
+    swap_rows<S>(al, bl);
+    swap_rows<S>(ah, bh);
+    a = __hiloint2double((int)ah, (int)al);
+    b = __hiloint2double((int)bh, (int)bl);
+}
+
+template <int S, typename T>
+__device__ __forceinline__ void swap_rows(cx<T>& a, cx<T>& b)
+{
+    swap_rows<S>(a.r, b.r);
+    swap_rows<S>(a.i, b.i);
+}
+
+// decimation in time, bit-reversed standard input, transposed output
+template <bool INV, typename T>
+__device__ __forceinline__ void dit64_to_trx(cx<T> (&x)[4], const Twiddles<T, 4>& w)
+{
+    dit64<INV, false, T, 4, 4>(x, w);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        swap_rows<4>(x[k], x[k + 2]);
+        const cx<T> m = cmul<INV>(x[k + 2], w.t4), lo = x[k];
+        x[k] = lo + m;
+        x[k + 2] = lo - m;
+    }
+    // position bit 4 now sits in slot bit 1: its twiddle factor e^{-i pi/2}
+    // (conjugated for the inverse) multiplies the pair (2, 3)
+#pragma unroll
+    for (int k = 0; k < 4; k += 2) {
+        swap_rows<5>(x[k], x[k + 1]);
+        cx<T> m = cmul<INV>(x[k + 1], w.t5lo);
+        if (k == 2) m = INV ? times_i(m) : times_mi(m);
+        const cx<T> lo = x[k];
+        x[k] = lo + m;
+        x[k + 1] = lo - m;
+    }
+}
+
+// decimation in frequency, natural standard input, transposed output
+template <bool INV, typename T>
+__device__ __forceinline__ void dif64_to_trx(cx<T> (&x)[4], const Twiddles<T, 4>& w)
+{
+#pragma unroll
+    for (int k = 0; k < 4; k += 2) {
+        swap_rows<5>(x[k], x[k + 1]);
+        const cx<T> lo = x[k], hi = x[k + 1];
+        x[k] = lo + hi;
+        x[k + 1] = cmul<INV>(lo - hi, w.t5);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        swap_rows<4>(x[k], x[k + 2]);
+        const cx<T> lo = x[k], hi = x[k + 2];
+        x[k] = lo + hi;
+        x[k + 2] = cmul<INV>(lo - hi, w.t4);
+    }
+    dif64<INV, false, T, 4, 3>(x, w);
+}
+
+// decimation in time, transposed input (as dif64_to_trx leaves it),
+// natural standard output
+template <bool INV, typename T>
+__device__ __forceinline__ void dit64_from_trx(cx<T> (&x)[4], const Twiddles<T, 4>& w)
+{
+    dit64<INV, false, T, 4, 4>(x, w);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const cx<T> m = cmul<INV>(x[k + 2], w.t4), lo = x[k];
+        x[k] = lo + m;
+        x[k + 2] = lo - m;
+        swap_rows<4>(x[k], x[k + 2]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k += 2) {
+        const cx<T> m = cmul<INV>(x[k + 1], w.t5), lo = x[k];
+        x[k] = lo + m;
+        x[k + 1] = lo - m;
+        swap_rows<5>(x[k], x[k + 1]);
+    }
+}
+
+// decimation in frequency, transposed input, bit-reversed standard output
+template <bool INV, typename T>
+__device__ __forceinline__ void dif64_from_trx(cx<T> (&x)[4], const Twiddles<T, 4>& w)
+{
+#pragma unroll
+    for (int k = 0; k < 4; k += 2) {
+        const cx<T> lo = x[k], hi = x[k + 1];
+        cx<T> m = cmul<INV>(lo - hi, w.t5lo);
+        if (k == 2) m = INV ? times_i(m) : times_mi(m);
+        x[k] = lo + hi;
+        x[k + 1] = m;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const cx<T> lo = x[k], hi = x[k + 2];
+        x[k] = lo + hi;
+        x[k + 2] = cmul<INV>(lo - hi, w.t4);
+    }
+    dif64<INV, false, T, 4, 3>(x, w);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) swap_rows<4>(x[k], x[k + 2]);
+#pragma unroll
+    for (int k = 0; k < 4; k += 2) swap_rows<5>(x[k], x[k + 1]);
+}
+
 template <typename T, int NK>
 struct FftShape {
     static constexpr int N = 2 * NK;            // padded length
@@ -289,6 +434,7 @@ struct FftShape {
     static constexpr int NA = R >= 2 ? R / 2 : 1;  // in-lane positions inside the window
     static constexpr int PITCH = NJ * 64 + 1;   // complex values per row pair in LDS
     static constexpr bool SWAP = sizeof(T) == 8 && NK >= 64;  // lane swaps for xor 16 / 32
+    static constexpr bool TRX = SWAP && R == 4 && P == 2;      // register-transposed swap stages
     static constexpr size_t lds() { return sizeof(cx<T>) * (NK / 2) * PITCH + sizeof(T) * 3 * N; }
 };
 
@@ -322,7 +468,7 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
 {
     using S = FftShape<T, NK>;
     constexpr int N = S::N, R = S::R, P = S::P, NJ = S::NJ, RPW = S::RPW, NA = S::NA, PITCH = S::PITCH;
-    constexpr bool SW = S::SWAP;
+    constexpr bool SW = S::SWAP, TRX = S::TRX;
     extern __shared__ unsigned char smem_raw[];
     cx<T>* A = reinterpret_cast<cx<T>*>(smem_raw);
     T* tab = reinterpret_cast<T*>(A + (NK / 2) * PITCH);  // S1 | S2 | K, N each
@@ -378,9 +524,21 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
             }
             if (q + 1 < RPW) load_rows(r + 1);
             fwd_inlane(x, tw.rev);
-            dit64<false, SW>(x, tw);
+            if constexpr (TRX) {
+                // transposed: lane bits 5, 4 carry k1, the slots position bits 5, 4;
+                // this pass keeps k1 = p + 2 jj, the lanes with bit 5 = p
+                dit64_to_trx<false>(x, tw);
+                if (((lane >> 5) & 1) == p) {
+                    const int jj = (lane >> 4) & 1;
 #pragma unroll
-            for (int jj = 0; jj < NJ; ++jj) A[r * PITCH + jj * 64 + lane] = x[p + P * jj];
+                    for (int k = 0; k < 4; ++k)
+                        A[r * PITCH + jj * 64 + ((lane & 15) | ((k >> 1) << 4) | ((k & 1) << 5))] = x[k];
+                }
+            } else {
+                dit64<false, SW>(x, tw);
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) A[r * PITCH + jj * 64 + lane] = x[p + P * jj];
+            }
         }
         __syncthreads();
 
@@ -407,17 +565,28 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
                 }
             }
             fwd_inlane(x, tw.nat);
-            dif64<false, SW>(x, tw);
             const T s2 = S2[k2];
-#pragma unroll
-            for (int k1 = 0; k1 < R; ++k1) {
-                const int kk = k1 + R * blane;
-                // W / 2 (the 2 of the unpacking), the 1/N^2 already in the tables
+            // W / 2 (the 2 of the unpacking), the 1/N^2 already in the tables
+            auto apply_w = [&](cx<T>& v, int kk) {
                 const T wgt = S1[kk] + s2 + KK[(kk - k2) & (N - 1)];
-                x[k1] = times_mi(x[k1]);
-                x[k1] = {x[k1].r * wgt, x[k1].i * wgt};
+                v = times_mi(v);
+                v = {v.r * wgt, v.i * wgt};
+            };
+            if constexpr (TRX) {
+                dif64_to_trx<false>(x, tw);
+                // slot k: output index br(position), position bits 4, 5 = k >> 1,
+                // k & 1 (bits 1, 0 after the reversal); k1 from lane bits 5, 4
+                const int k1l = ((lane >> 5) & 1) | (((lane >> 4) & 1) << 1);
+                const int brl = (int)(__builtin_bitreverse32((unsigned)(lane & 15)) >> 26);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) apply_w(x[k], k1l + R * (brl | ((k >> 1) << 1) | (k & 1)));
+                dit64_from_trx<true>(x, tw);
+            } else {
+                dif64<false, SW>(x, tw);
+#pragma unroll
+                for (int k1 = 0; k1 < R; ++k1) apply_w(x[k1], k1 + R * blane);
+                dit64<true, SW>(x, tw);
             }
-            dit64<true, SW>(x, tw);
             inv_inlane(x, tw.nat);
 #pragma unroll
             for (int a = 0; a < NA; ++a) {
@@ -442,9 +611,20 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
             cx<T> z[R];
 #pragma unroll
             for (int k = 0; k < R; ++k) z[k] = {T(0), T(0)};
+            if constexpr (TRX) {
+                // read in the transposed layout (see the forward rows)
+                if (((lane >> 5) & 1) == p) {
+                    const int jj = (lane >> 4) & 1;
 #pragma unroll
-            for (int jj = 0; jj < NJ; ++jj) z[p + P * jj] = A[r * PITCH + jj * 64 + lane];
-            dif64<true, SW>(z, tw);
+                    for (int k = 0; k < 4; ++k)
+                        z[k] = A[r * PITCH + jj * 64 + ((lane & 15) | ((k >> 1) << 4) | ((k & 1) << 5))];
+                }
+                dif64_from_trx<true>(z, tw);
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) z[p + P * jj] = A[r * PITCH + jj * 64 + lane];
+                dif64<true, SW>(z, tw);
+            }
             inv_inlane(z, tw.rev);
 #pragma unroll
             for (int a = 0; a < NA; ++a) acc[q][a] = acc[q][a] + z[a];
