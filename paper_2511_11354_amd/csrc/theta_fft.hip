@@ -255,13 +255,22 @@ __device__ __forceinline__ void dit64(cx<T> (&x)[R], const Twiddles<T, R>& w)
     }
 }
 
-// In-lane part of a forward transform whose input is zero beyond the first
-// half (x[a] = 0 for a >= R/2): x[a] -> DFT_R over a, times the twiddles.
+// In-lane part of a forward transform whose input is zero past the plane
+// (x[a] = 0 for 64 a >= nk = N/2: a >= 1 at R = 2, a >= 2 at R = 3, 4):
+// x[a] -> DFT_R over a, times the twiddles.
 template <typename T, int R>
 __device__ __forceinline__ void fwd_inlane(cx<T> (&x)[R], const cx<T> (&tw)[R])
 {
+    constexpr T h3 = T(0.86602540378443864676);  // sin(pi/3)
     if constexpr (R == 2) {
         x[1] = x[0] * tw[1];
+    } else if constexpr (R == 3) {
+        const cx<T> a = x[0], b = x[1];
+        const cx<T> c = {a.r - T(0.5) * b.r, a.i - T(0.5) * b.i};  // a - b/2
+        const cx<T> e = {h3 * b.r, h3 * b.i};                        // (sqrt 3 / 2) b
+        x[0] = a + b;
+        x[1] = (c + times_mi(e)) * tw[1];
+        x[2] = (c + times_i(e)) * tw[2];
     } else if constexpr (R == 4) {
         const cx<T> a = x[0], b = x[1];
         x[0] = a + b;
@@ -271,15 +280,24 @@ __device__ __forceinline__ void fwd_inlane(cx<T> (&x)[R], const cx<T> (&tw)[R])
     }
 }
 
-// In-lane part of an inverse transform of which only the first half of the
-// output is kept: conjugate twiddles, then the inverse DFT_R into x[0 .. R/2).
+// In-lane part of an inverse transform of which only the plane's positions
+// are kept (64 a < nk): conjugate twiddles, then the inverse DFT_R into
+// x[0 .. NA).
 template <typename T, int R>
 __device__ __forceinline__ void inv_inlane(cx<T> (&z)[R], const cx<T> (&tw)[R])
 {
+    constexpr T h3 = T(0.86602540378443864676);
 #pragma unroll
     for (int k = 1; k < R; ++k) z[k] = z[k] * conjg(tw[k]);
     if constexpr (R == 2) {
         z[0] = z[0] + z[1];
+    } else if constexpr (R == 3) {
+        const cx<T> s12 = z[1] + z[2], d12 = z[1] - z[2];
+        const cx<T> c0 = z[0] + s12;
+        const cx<T> c1 = cx<T>{z[0].r - T(0.5) * s12.r, z[0].i - T(0.5) * s12.i} +
+                         times_i(cx<T>{h3 * d12.r, h3 * d12.i});
+        z[0] = c0;
+        z[1] = c1;
     } else if constexpr (R == 4) {
         const cx<T> c0 = (z[0] + z[2]) + (z[1] + z[3]);
         const cx<T> c1 = (z[0] - z[2]) + times_i(z[1] - z[3]);
@@ -431,7 +449,7 @@ struct FftShape {
     static constexpr int NJ = R / P;            // in-lane indices k1 per pass (k1 = p + P jj)
     static constexpr int NW = NK / 16;          // wavefronts
     static constexpr int RPW = NK / 2 / NW;     // row pairs per wavefront
-    static constexpr int NA = R >= 2 ? R / 2 : 1;  // in-lane positions inside the window
+    static constexpr int NA = (NK + 63) / 64;   // in-lane positions inside the window
     static constexpr int PITCH = NJ * 64 + 1;   // complex values per row pair in LDS
     static constexpr bool SWAP = sizeof(T) == 8 && NK >= 64;  // lane swaps for xor 16 / 32
     static constexpr bool TRX = SWAP && R == 4 && P == 2;      // register-transposed swap stages
@@ -549,7 +567,7 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
         const T* KK = tab + 2 * N;
 #pragma unroll 1
         for (int c = wave; c < ncol; c += S::NW) {
-            const int k2 = p + P * c, k2p = (N - k2) & (N - 1);
+            const int k2 = p + P * c, k2p = k2 == 0 ? 0 : N - k2;
             const int s_a = ((k2 % R) / P) * 64 + k2 / R;
             const int s_b = ((k2p % R) / P) * 64 + k2p / R;
             cx<T> x[R];
@@ -568,7 +586,8 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
             const T s2 = S2[k2];
             // W / 2 (the 2 of the unpacking), the 1/N^2 already in the tables
             auto apply_w = [&](cx<T>& v, int kk) {
-                const T wgt = S1[kk] + s2 + KK[(kk - k2) & (N - 1)];
+                const int dk = kk - k2;
+                const T wgt = S1[kk] + s2 + KK[dk < 0 ? dk + N : dk];
                 v = times_mi(v);
                 v = {v.r * wgt, v.i * wgt};
             };
@@ -679,7 +698,8 @@ hipError_t go_fft(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, 
 
 bool theta_fft_ok(const ThetaArgs& a)
 {
-    return a.ksem == nullptr && (a.nk == 32 || a.nk == 64 || a.nk == 128) && a.precision != WIG2_BF16X2;
+    return a.ksem == nullptr && (a.nk == 32 || a.nk == 64 || a.nk == 96 || a.nk == 128) &&
+           a.precision != WIG2_BF16X2;
 }
 
 template <typename T>
@@ -694,6 +714,7 @@ hipError_t launch_theta_fft(const ThetaArgs& a, const T* u, const T* v, T* out, 
     switch (a.nk) {
     case 32: return go_fft<T, 32>(a, u, v, out, mode, tau, st);
     case 64: return go_fft<T, 64>(a, u, v, out, mode, tau, st);
+    case 96: return go_fft<T, 96>(a, u, v, out, mode, tau, st);
     default: return go_fft<T, 128>(a, u, v, out, mode, tau, st);
     }
 }
