@@ -22,7 +22,8 @@
 //    inverse column transform, repack.
 //  * inverse row transforms.  The real and imaginary parts are again the
 //    two rows.  Both halves add into registers.
-// Each transform has N = 64 R points and is done by one wavefront:
+// Each transform has N = 64 R points (R = 1, 2, 3, 4 for nk = 32, 64, 96,
+// 128) and is done by one wavefront:
 //  * the in-lane R-point DFT and its twiddles (four-step decomposition);
 //  * a 64-point radix-2 transform across the lanes, by lane exchanges on
 //    the vector ALUs (DPP moves and row / half swaps).
