@@ -200,7 +200,11 @@ int wig2_observables(wig2_ctx* ctx, wig2_obs* obs, double* n1, double* n12, doub
  *    with nk = 256 in FP64 or BF16X2 (several workgroups share a plane
  *    there): WIG2_EINVAL.
  *  wig2_advect: one spline sweep along x_dim (dim 1 or 2) by time s:
- *    out(x, p) = in(x_dim - s p_dim / m, p).  in != out. */
+ *    out(x, p) = in(x_dim - s p_dim / m, p).  in != out.
+ * Both run asynchronously on the context's stream (the one passed to
+ * wig2_create, else the context's own): work that other streams do on
+ * in_dev or out_dev must be complete (or ordered before the call by the
+ * caller) when the call is made. */
 int wig2_theta(wig2_ctx* ctx, const void* in_dev, void* out_dev);
 int wig2_advect(wig2_ctx* ctx, int32_t dim, double s, const void* in_dev, void* out_dev);
 

@@ -148,9 +148,15 @@ def _ptr(a):
 
 
 def _dev(t):
-    """Device pointer of a torch tensor (or an int address)."""
+    """Device pointer of a torch tensor (or an int address).  The library
+    works on its context's stream; work that torch has queued on the
+    tensor's current stream (the fill or cast that produced it) is waited
+    for first, so the call sees the finished tensor."""
     if hasattr(t, "data_ptr"):
         assert t.is_cuda and t.is_contiguous()
+        import torch
+
+        torch.cuda.current_stream(t.device).synchronize()
         return ctypes.c_void_p(t.data_ptr())
     return ctypes.c_void_p(int(t))
 

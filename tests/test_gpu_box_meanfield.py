@@ -72,7 +72,8 @@ def test_box_meanfield_theta_matches_oracle(orc, nx, nk, cells, precision, pair,
     nomf = orc.theta_dense(g, tb["K"], tb["K"], f) + (orc.theta12_sem(g, tb["v12_sem"], f) if pair else 0.0)
     dt = torch.float64 if precision == "fp64" else torch.float32
     fin = torch.from_numpy(f).to(device="cuda", dtype=dt)
-    out = torch.empty_like(fin)
+    out = torch.full_like(fin, float("nan"))
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     print(f"box mean field theta {precision} nx={nx} nk={nk} pair={pair} xc={xc}: ", end="", flush=True)
     s.theta(fin, out)
     torch.cuda.synchronize()
@@ -88,7 +89,8 @@ def test_box_meanfield_theta_bf16x2_panel(orc):
     f = I.symmetrised_pair(x, p, a=(-2.0, 1.5), q=(0.3, -0.4))
     ref = oracle_theta(orc, g, f, True, True)
     fin = torch.from_numpy(f).to(device="cuda", dtype=torch.float32)
-    out = torch.empty_like(fin)
+    out = torch.full_like(fin, float("nan"))
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     s.theta(fin, out)
     torch.cuda.synchronize()
     e = eps_inf(out.double().cpu().numpy(), ref)

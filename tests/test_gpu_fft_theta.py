@@ -52,7 +52,8 @@ def test_fft_theta_matches_oracle(orc, nx, nk, pot, two):
     f = I.random_field((nx, nx, nk, nk), seed=nx * 100 + nk)
     tb = orc.tables(g, POT[pot], V12 if two else None)
     ref = orc.theta_periodic(g, tb["sig_ext"], tb["sig_ext"], tb["vhat12"], f, two)
-    out = torch.empty(f.shape, dtype=torch.float64, device="cuda")
+    out = torch.full(f.shape, float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     print(f"fft theta nx={nx} nk={nk} {pot} two={two}: ", end="", flush=True)
     s.theta(torch.from_numpy(f).cuda(), out)
     torch.cuda.synchronize()
@@ -67,7 +68,8 @@ def test_fft_theta_fp32(orc, nx, nk):
     f = I.random_field((nx, nx, nk, nk), seed=11 + nk)
     tb = orc.tables(g, POT["dw"], V12)
     ref = orc.theta_periodic(g, tb["sig_ext"], tb["sig_ext"], tb["vhat12"], f, True)
-    out = torch.empty(f.shape, dtype=torch.float32, device="cuda")
+    out = torch.full(f.shape, float("nan"), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     s.theta(torch.from_numpy(f).float().cuda(), out)
     torch.cuda.synchronize()
     e = eps_inf(out.double().cpu().numpy(), ref)

@@ -50,7 +50,8 @@ def test_panel_theta_matches_oracle(orc, precision, potential):
     ref = orc.theta_dense(g, K, K, f)
     dt = torch.float64 if precision == "fp64" else torch.float32
     fin = torch.from_numpy(f).to(dtype=dt, device="cuda")
-    out = torch.empty_like(fin)
+    out = torch.full_like(fin, float("nan"))  # every point must be written
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     s.theta(fin, out)
     torch.cuda.synchronize()
     e = eps_inf(out.double().cpu().numpy(), ref)
@@ -123,7 +124,8 @@ def test_panel_full_shape_sampled(orc, precision):
     print("129^2 x 256^2 input ready", flush=True)
     dt = torch.float64 if precision == "fp64" else torch.float32
     fin = torch.from_numpy(f0).to(dtype=dt, device="cuda")
-    out = torch.empty_like(fin)
+    out = torch.full_like(fin, float("nan"))  # every point must be written
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     s.theta(fin, out)
     torch.cuda.synchronize()
     del fin

@@ -64,7 +64,8 @@ def test_theta_fp64_matches_oracle(orc, nx, nk, pot):
     f = I.random_field((nx, nx, nk, nk), seed=nx * 100 + nk)
     tb = orc.tables(g, vext, v12)
     ref = orc.theta_periodic(g, tb["sig_ext"], tb["sig_ext"], tb["vhat12"], f, True)
-    out = torch.empty((nx, nx, nk, nk), dtype=torch.float64, device="cuda")
+    out = torch.full((nx, nx, nk, nk), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     s.theta(dev(f), out)
     torch.cuda.synchronize()
     e = eps_inf(host(out), ref)
@@ -100,7 +101,8 @@ def test_theta_reduced_precision(orc, precision, tol):
     f = I.random_field((nx, nx, nk, nk), seed=7)
     tb = orc.tables(g, vext, v12)
     ref = orc.theta_periodic(g, tb["sig_ext"], tb["sig_ext"], tb["vhat12"], f, True)
-    out = torch.empty(f.shape, dtype=torch.float32, device="cuda")
+    out = torch.full(f.shape, float("nan"), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     s.theta(dev(f, torch.float32), out)
     torch.cuda.synchronize()
     e = eps_inf(host(out), ref)

@@ -58,7 +58,8 @@ def test_box_pair_theta_matches_oracle(orc, nx, nk, cells, precision):
     pair = orc.theta12_sem(g, tb["v12_sem"], f)
     dt = torch.float64 if precision == "fp64" else torch.float32
     fin = torch.from_numpy(f).to(device="cuda", dtype=dt)
-    out = torch.empty_like(fin)
+    out = torch.full_like(fin, float("nan"))  # every point must be written
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     print(f"box pair theta {precision} nx={nx} nk={nk}: ", end="", flush=True)
     s.theta(fin, out)
     torch.cuda.synchronize()
@@ -77,7 +78,8 @@ def test_box_pair_theta_in_place(orc, precision):
     f = I.symmetrised_pair(x, p, a=(-2.0, 1.5), q=(0.3, -0.4))
     dt = torch.float64 if precision == "fp64" else torch.float32
     fin = torch.from_numpy(f).to(device="cuda", dtype=dt)
-    out = torch.empty_like(fin)
+    out = torch.full_like(fin, float("nan"))  # every point must be written
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     s.theta(fin, out)
     s.theta(fin, fin)
     torch.cuda.synchronize()

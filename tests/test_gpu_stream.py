@@ -56,9 +56,11 @@ def test_stream_theta_matches_oracle(orc, nx, nk, pot, two):
     fin = torch.from_numpy(f).cuda()
     # NaN-filled outputs: every point must be written
     out = torch.full_like(fin, float("nan"))
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     s.theta(fin, out)
     s.set_theta_path("general")
     out_g = torch.full_like(fin, float("nan"))
+    torch.cuda.synchronize()  # the fill runs on torch's stream, Theta on the context's
     s.theta(fin, out_g)
     torch.cuda.synchronize()
     got, gen = out.cpu().numpy(), out_g.cpu().numpy()
