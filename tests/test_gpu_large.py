@@ -35,9 +35,10 @@ def big(orc):
 def test_theta_sampled_planes(orc, big):
     w, s, g, f0, tb = big
     fin = torch.from_numpy(f0).cuda()
-    out = torch.empty_like(fin)
+    out = torch.full_like(fin, float("nan"))  # every point must be written
     s.theta(fin, out)
     torch.cuda.synchronize()
+    assert not bool(torch.isnan(out).any())
     got = out.cpu().numpy()
     del out, fin
     rng = np.random.default_rng(1)
@@ -64,9 +65,10 @@ def test_theta_sampled_planes(orc, big):
 def test_advect_sampled_lines(orc, big, dim):
     w, s, g, f0, tb = big
     fin = torch.from_numpy(f0).cuda()
-    out = torch.empty_like(fin)
+    out = torch.full_like(fin, float("nan"))  # every point must be written
     s.advect(dim, 0.5 * w.dt, fin, out)
     torch.cuda.synchronize()
+    assert not bool(torch.isnan(out).any())
     got = out.cpu().numpy()
     del out, fin
     nk2 = w.nk * w.nk

@@ -87,7 +87,7 @@ def test_theta_single_body_closed_form(orc):
           * np.sin((X1 + r0) * P1)
           + np.pi**-2.5 * np.exp(-3 * (X2 + r0) ** 2 / 4 - P2**2 - (X1 + r0) ** 2 / 2 - 2 * P1**2)
           * np.sin((X2 + r0) * P2))
-    out = torch.empty(f.shape, dtype=torch.float64, device="cuda")
+    out = torch.full(f.shape, float("nan"), dtype=torch.float64, device="cuda")
     s.theta(dev(f), out)
     torch.cuda.synchronize()
     assert np.max(np.abs(host(out) - ex)) <= 1e-15
@@ -128,7 +128,7 @@ def test_advect_fp64_matches_oracle(orc, nx, nk, periodic, s, dim):
     sol, g = make(orc, nx, nk, **kw)
     f = I.random_field((nx, nx, nk, nk), seed=11 + nx)
     ref = orc.advect(g, dim, s, f)
-    out = torch.empty(f.shape, dtype=torch.float64, device="cuda")
+    out = torch.full(f.shape, float("nan"), dtype=torch.float64, device="cuda")
     sol.advect(dim, s, dev(f), out)
     torch.cuda.synchronize()
     e = eps_inf(host(out), ref)
@@ -141,7 +141,7 @@ def test_advect_fp32(orc, nx, nk, dim):
     sol, g = make(orc, nx, nk, precision="fp32")
     f = I.random_field((nx, nx, nk, nk), seed=5)
     ref = orc.advect(g, dim, 0.02, f)
-    out = torch.empty(f.shape, dtype=torch.float32, device="cuda")
+    out = torch.full(f.shape, float("nan"), dtype=torch.float32, device="cuda")
     sol.advect(dim, 0.02, dev(f, torch.float32), out)
     torch.cuda.synchronize()
     assert eps_inf(host(out), ref) <= 2e-6
