@@ -65,9 +65,12 @@ __device__ __forceinline__ cx<T> times_mi(cx<T> a) { return {a.i, -a.r}; }
 // row_mirror (vector-ALU moves).  For xor 16 and xor 32 the row and half
 // swaps (v_permlane16_swap, v_permlane32_swap) give every lane both members
 // of its pair (SWAP), so no exchange goes through the LDS crossbar, whose
-// issue rate bounds the FP64 kernels at nk >= 64; the FP32 and small-plane
-// variants, with more waves per SIMD and less vector-ALU headroom, keep
-// ds_bpermute for those two stages (measured faster there).
+// issue rate bounds the FP64 kernels at nk >= 64.  At nk = 128 (four
+// sequences per lane, FP64 and FP32) the swaps trade a slot bit for the lane
+// bit instead (register-transposed stages, no copies).  FP32 at nk <= 96 and
+// FP64 at nk = 32, with more waves per SIMD and less vector-ALU headroom,
+// keep ds_bpermute for those two stages (measured faster there than the
+// copy-and-swap form).
 __device__ __forceinline__ int logical_lane(int L) { return (L & 0x38) | ((L ^ (L >> 1)) & 7); }
 
 template <int CTRL>
@@ -342,6 +345,15 @@ __device__ __forceinline__ void swap_rows(double& a, double& b)
     b = __hiloint2double((int)bh, (int)bl);
 }
 
+template <int S>
+__device__ __forceinline__ void swap_rows(float& a, float& b)
+{
+    unsigned au = __float_as_uint(a), bu = __float_as_uint(b);
+    swap_rows<S>(au, bu);
+    a = __uint_as_float(au);
+    b = __uint_as_float(bu);
+}
+
 template <int S, typename T>
 __device__ __forceinline__ void swap_rows(cx<T>& a, cx<T>& b)
 {
@@ -453,7 +465,7 @@ struct FftShape {
     static constexpr int NA = (NK + 63) / 64;   // in-lane positions inside the window
     static constexpr int PITCH = NJ * 64 + 1;   // complex values per row pair in LDS
     static constexpr bool SWAP = sizeof(T) == 8 && NK >= 64;  // lane swaps for xor 16 / 32
-    static constexpr bool TRX = SWAP && R == 4 && P == 2;      // register-transposed swap stages
+    static constexpr bool TRX = R == 4;  // register-transposed swap stages (nk = 128)
     static constexpr size_t lds() { return sizeof(cx<T>) * (NK / 2) * PITCH + sizeof(T) * 3 * N; }
 };
 
@@ -545,10 +557,11 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
             fwd_inlane(x, tw.rev);
             if constexpr (TRX) {
                 // transposed: lane bits 5, 4 carry k1, the slots position bits 5, 4;
-                // this pass keeps k1 = p + 2 jj, the lanes with bit 5 = p
+                // this pass keeps k1 = p + P jj
                 dit64_to_trx<false>(x, tw);
-                if (((lane >> 5) & 1) == p) {
-                    const int jj = (lane >> 4) & 1;
+                const int k1l = ((lane >> 5) & 1) | (((lane >> 4) & 1) << 1);
+                if (k1l % P == p) {
+                    const int jj = k1l / P;
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
                         A[r * PITCH + jj * 64 + ((lane & 15) | ((k >> 1) << 4) | ((k & 1) << 5))] = x[k];
@@ -633,8 +646,9 @@ __global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double
             for (int k = 0; k < R; ++k) z[k] = {T(0), T(0)};
             if constexpr (TRX) {
                 // read in the transposed layout (see the forward rows)
-                if (((lane >> 5) & 1) == p) {
-                    const int jj = (lane >> 4) & 1;
+                const int k1l = ((lane >> 5) & 1) | (((lane >> 4) & 1) << 1);
+                if (k1l % P == p) {
+                    const int jj = k1l / P;
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
                         z[k] = A[r * PITCH + jj * 64 + ((lane & 15) | ((k >> 1) << 4) | ((k & 1) << 5))];
