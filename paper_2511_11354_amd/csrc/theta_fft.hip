@@ -454,13 +454,23 @@ __device__ __forceinline__ void dif64_from_trx(cx<T> (&x)[4], const Twiddles<T, 
     for (int k = 0; k < 4; k += 2) swap_rows<5>(x[k], x[k + 1]);
 }
 
+// Wavefronts per workgroup: nk/16 (eight row pairs each); FP32 at nk >= 64
+// takes twice as many (four row pairs each: 51-75 VGPRs, more waves to hide
+// the exchange and LDS latency; measured 3-27% faster there, 6% slower at
+// nk = 32).  FP64 has no register room for it.
+template <typename T, int NK>
+constexpr int fft_waves()
+{
+    return (sizeof(T) == 4 && NK >= 64 ? 2 : 1) * NK / 16;
+}
+
 template <typename T, int NK>
 struct FftShape {
     static constexpr int N = 2 * NK;            // padded length
     static constexpr int R = N / 64;            // values per lane
     static constexpr int P = (sizeof(T) == 8 && NK == 128) ? 2 : 1;  // spectrum passes
     static constexpr int NJ = R / P;            // in-lane indices k1 per pass (k1 = p + P jj)
-    static constexpr int NW = NK / 16;          // wavefronts
+    static constexpr int NW = fft_waves<T, NK>();  // wavefronts
     static constexpr int RPW = NK / 2 / NW;     // row pairs per wavefront
     static constexpr int NA = (NK + 63) / 64;   // in-lane positions inside the window
     static constexpr int PITCH = NJ * 64 + 1;   // complex values per row pair in LDS
@@ -494,7 +504,7 @@ __global__ void __launch_bounds__(256) k_fft_symbols(int nx, int nk, const doubl
 // out = alpha Theta (u + beta v) + cu u + cv v on plane blockIdx.x; out may
 // be u (every read of the plane precedes its writes, all in this workgroup).
 template <typename T, int NK>
-__global__ void __launch_bounds__(NK / 16 * 64) k_theta_fft(int nx, const double* __restrict__ sym, const T* u,
+__global__ void __launch_bounds__((fft_waves<T, NK>() * 64)) k_theta_fft(int nx, const double* __restrict__ sym, const T* u,
                                                            const T* v, T* out, T beta, T alpha, T cu, T cv)
 {
     using S = FftShape<T, NK>;
