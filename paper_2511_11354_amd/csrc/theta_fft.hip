@@ -457,10 +457,13 @@ __device__ __forceinline__ void dif64_from_trx(cx<T> (&x)[4], const Twiddles<T, 
 // Wavefronts per workgroup: nk/16 (eight row pairs each); FP32 at nk >= 64
 // takes twice as many (four row pairs each: 51-75 VGPRs, more waves to hide
 // the exchange and LDS latency; measured 3-27% faster there, 6% slower at
-// nk = 32).  FP64 has no register room for it.
+// nk = 32), FP64 at nk = 96 eight (six row pairs each: two waves on every
+// SIMD instead of one or two; 17% faster).  FP64 at nk = 128 has no
+// register room for more.
 template <typename T, int NK>
 constexpr int fft_waves()
 {
+    if (sizeof(T) == 8 && NK == 96) return 8;
     return (sizeof(T) == 4 && NK >= 64 ? 2 : 1) * NK / 16;
 }
 
