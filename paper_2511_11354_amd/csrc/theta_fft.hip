@@ -1,5 +1,5 @@
 // Theta on the torus by fast Fourier transforms (the FFT-accelerated route of
-// the two-body cost statement in Sec. 3.1.2, with N = 2 nk points per
+// the two-body cost statement in Sec. 3.1.2, with N >= 2 nk points per
 // momentum direction as Sec. 3.1 sets the mesh up for).
 //
 // On a momentum plane (i1, i2) the three pseudo-difference terms of Sec. 3.1
@@ -7,8 +7,9 @@
 // (particle 2's symbol s2), the columns (particle 1's s1) and the
 // anti-diagonals (the pair kernel kap, shifting p1 and p2 in opposite
 // directions).  Together they form one 2-D linear convolution.  Padding both
-// momentum indices with zeros to N = 2 nk makes the cyclic convolution on the
-// N x N torus equal to it on the nk x nk window, so
+// momentum indices with zeros to N >= 2 nk (N = 2 nk rounded up to a
+// multiple of 64) makes the cyclic convolution on the N x N torus equal to
+// it on the nk x nk window, so
 //   Theta f = IFFT2( W . FFT2(f) ),
 //   W(k1, k2) = -2i [S1(k1) + S2(k2) + K((k1 - k2) mod N)],
 //   S(k) = sum_{m >= 1} s_m sin(2 pi k m / N),
@@ -469,7 +470,7 @@ constexpr int fft_waves()
 
 template <typename T, int NK>
 struct FftShape {
-    static constexpr int N = 2 * NK;            // padded length
+    static constexpr int N = fft_len(NK);       // padded length
     static constexpr int R = N / 64;            // values per lane
     static constexpr int P = (sizeof(T) == 8 && NK == 128) ? 2 : 1;  // spectrum passes
     static constexpr int NJ = R / P;            // in-lane indices k1 per pass (k1 = p + P jj)
@@ -483,15 +484,15 @@ struct FftShape {
 };
 
 // Plane symbols: sym[(w nx + row) N + k] = S_w(k) / N^2 for w = 0 (s1, row
-// i1), 1 (s2, row i2), 2 (kap, row (i1 - i2) mod nx).  The 1/N^2 is the
-// normalisation of the two inverse transforms.
+// i1), 1 (s2, row i2), 2 (kap, row (i1 - i2) mod nx), N = fft_len(nk).  The
+// 1/N^2 is the normalisation of the two inverse transforms.
 __global__ void __launch_bounds__(256) k_fft_symbols(int nx, int nk, const double* __restrict__ sig1,
                                                     const double* __restrict__ sig2,
                                                     const double* __restrict__ kap, double* __restrict__ sym)
 {
     __shared__ double sn[2 * kMaxThetaNk];
     __shared__ double sv[kMaxThetaNk];
-    const int N = 2 * nk, row = blockIdx.x, which = blockIdx.y;
+    const int N = fft_len(nk), row = blockIdx.x, which = blockIdx.y;
     const double* s = which == 0 ? sig1 : which == 1 ? sig2 : kap;
     for (int t = threadIdx.x; t < N; t += blockDim.x) sn[t] = sinpi(2.0 * t / N);
     for (int t = threadIdx.x; t < nk; t += blockDim.x) sv[t] = s ? s[(long)row * nk + t] : 0.0;
@@ -726,7 +727,7 @@ hipError_t go_fft(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, 
 
 bool theta_fft_ok(const ThetaArgs& a)
 {
-    return a.ksem == nullptr && (a.nk == 32 || a.nk == 64 || a.nk == 96 || a.nk == 128) &&
+    return a.ksem == nullptr && (a.nk == 32 || a.nk == 48 || a.nk == 64 || a.nk == 96 || a.nk == 128) &&
            a.precision != WIG2_BF16X2;
 }
 
@@ -741,6 +742,7 @@ hipError_t launch_theta_fft(const ThetaArgs& a, const T* u, const T* v, T* out, 
     if (e != hipSuccess) return e;
     switch (a.nk) {
     case 32: return go_fft<T, 32>(a, u, v, out, mode, tau, st);
+    case 48: return go_fft<T, 48>(a, u, v, out, mode, tau, st);
     case 64: return go_fft<T, 64>(a, u, v, out, mode, tau, st);
     case 96: return go_fft<T, 96>(a, u, v, out, mode, tau, st);
     default: return go_fft<T, 128>(a, u, v, out, mode, tau, st);
