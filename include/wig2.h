@@ -278,7 +278,7 @@ int wig2_band(const wig2_ctx* ctx);
  * W(k1, k2) = -2i [S1(k1) + S2(k2) +
  * K(k1 - k2)], S(k) = sum_m s_m sin(2 pi k m / N).  The result equals the
  * direct sums up to rounding, for any single-body band (mean field
- * included).  Needs a torus, nk in {32, 48, 64, 96, 128} and FP64 or FP32 (else
+ * included).  Needs a torus, nk in {16, 32, 48, 64, 96, 128} and FP64 or FP32 (else
  * WIG2_ENOTSUP).  Heun runs as its two stages.  On MI355X it is slower than
  * the direct products at every one of these sizes. */
 enum { WIG2_THETA_AUTO = 0, WIG2_THETA_GENERAL = 1, WIG2_THETA_STREAM = 2, WIG2_THETA_PANEL = 3, WIG2_THETA_FFT = 4 };

@@ -1351,7 +1351,7 @@ int wig2_set_theta_path(wig2_ctx* c, int32_t path)
 {
     if (!c || path < WIG2_THETA_AUTO || path > WIG2_THETA_FFT || path == WIG2_THETA_PANEL) return WIG2_EINVAL;
     if (path == WIG2_THETA_FFT && (!c->fft_sym_d || !theta_fft_ok(theta_args(c))))
-        return fail(c, WIG2_ENOTSUP, "FFT Theta needs a torus, nk in {32,48,64,96,128} and FP64 or FP32");
+        return fail(c, WIG2_ENOTSUP, "FFT Theta needs a torus, nk in {16,32,48,64,96,128} and FP64 or FP32");
     if (path == WIG2_THETA_STREAM && c->has_pot && !theta_stream_ok(theta_args(c)))
         return fail(c, WIG2_ENOTSUP, "streaming Theta needs a torus, nk in {32,48,64,96,128} (BF16X2: "
                                      "{32,64,96,128}) and a single-body band of at most 4 modes");

@@ -103,7 +103,7 @@ template <typename T>
 hipError_t launch_theta_heun(const ThetaArgs& a, const T* x, T* out, double tau, hipStream_t st);
 
 // Theta by 2-D FFT convolution of each momentum plane (theta_fft.hip):
-// torus, nk in {32, 48, 64, 96, 128}, FP64 / FP32, any single-body band.
+// torus, nk in {16, 32, 48, 64, 96, 128}, FP64 / FP32, any single-body band.
 // Same modes as launch_theta (0: out = Theta u; 1: out = u + tau/2 (v +
 // Theta (u + tau v))).  Padded transform length: 2 nk rounded up to a
 // multiple of the 64 lanes.

@@ -23,8 +23,8 @@
 //    inverse column transform, repack.
 //  * inverse row transforms.  The real and imaginary parts are again the
 //    two rows.  Both halves add into registers.
-// Each transform has N = 64 R points (R = 1, 2, 3, 4 for nk = 32, 64, 96,
-// 128) and is done by one wavefront:
+// Each transform has N = 64 R points (R = 1, 1, 2, 2, 3, 4 for nk = 16, 32,
+// 48, 64, 96, 128) and is done by one wavefront:
 //  * the in-lane R-point DFT and its twiddles (four-step decomposition);
 //  * a 64-point radix-2 transform across the lanes, by lane exchanges on
 //    the vector ALUs (DPP moves and row / half swaps).
@@ -727,7 +727,8 @@ hipError_t go_fft(const ThetaArgs& a, const T* u, const T* v, T* out, int mode, 
 
 bool theta_fft_ok(const ThetaArgs& a)
 {
-    return a.ksem == nullptr && (a.nk == 32 || a.nk == 48 || a.nk == 64 || a.nk == 96 || a.nk == 128) &&
+    return a.ksem == nullptr &&
+           (a.nk == 16 || a.nk == 32 || a.nk == 48 || a.nk == 64 || a.nk == 96 || a.nk == 128) &&
            a.precision != WIG2_BF16X2;
 }
 
@@ -741,6 +742,7 @@ hipError_t launch_theta_fft(const ThetaArgs& a, const T* u, const T* v, T* out, 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (a.nk) {
+    case 16: return go_fft<T, 16>(a, u, v, out, mode, tau, st);
     case 32: return go_fft<T, 32>(a, u, v, out, mode, tau, st);
     case 48: return go_fft<T, 48>(a, u, v, out, mode, tau, st);
     case 64: return go_fft<T, 64>(a, u, v, out, mode, tau, st);

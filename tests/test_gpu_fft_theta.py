@@ -1,8 +1,8 @@
 """The FFT route to Theta on the torus (the FFT-accelerated two-body cost of
 Sec. 3.1.2): each momentum plane's row, column and anti-diagonal
 pseudo-differences as one 2-D convolution, zero-padded to N = 2 nk
-(nk = 32, 48, 64, 96, 128; N = 2 nk rounded up to 64 R with an in-lane radix
-R = 1, 2, 2, 3, 4),
+(nk = 16, 32, 48, 64, 96, 128; N = 2 nk rounded up to 64 R with an in-lane
+radix R = 1, 1, 2, 2, 3, 4),
 IFFT2(W . FFT2(f)).  Checked against the FP64 oracle's direct sums for single
 applications, whole Strang and Lawson steps and the Hartree mean field, where
 the single-body symbols are dense.  Also checked against the direct MFMA
@@ -47,7 +47,7 @@ def solver(orc, nx, nk, *, pot="cos", two=True, precision="fp64", scheme="strang
 
 @pytest.mark.parametrize("nx,nk,pot,two", [(8, 32, "cos", True), (6, 64, "dw", True), (4, 128, "cos", True),
                                            (5, 128, "dw", True), (6, 64, "dw", False), (5, 96, "dw", True),
-                                           (7, 48, "cos", True)])
+                                           (7, 48, "cos", True), (9, 16, "dw", True)])
 def test_fft_theta_matches_oracle(orc, nx, nk, pot, two):
     s, g = solver(orc, nx, nk, pot=pot, two=two)
     assert s.theta_path() == "fft"
@@ -81,7 +81,7 @@ def test_fft_theta_fp32(orc, nx, nk):
 
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("scheme", ["strang", "lawson"])
-@pytest.mark.parametrize("nx,nk,lam", [(8, 32, 0.0), (7, 48, 1.0), (6, 64, 1.0), (5, 96, 1.0), (5, 128, 1.0),
+@pytest.mark.parametrize("nx,nk,lam", [(10, 16, 1.0), (8, 32, 0.0), (7, 48, 1.0), (6, 64, 1.0), (5, 96, 1.0), (5, 128, 1.0),
                                        (4, 128, 0.0)])
 def test_fft_steps_match_oracle(orc, scheme, nx, nk, lam):
     s, g = solver(orc, nx, nk, scheme=scheme, lam=lam, dt=0.005)
@@ -125,7 +125,8 @@ def test_fft_matches_stream_at_full_size():
 def test_fft_path_rejected_where_it_does_not_apply():
     from paper_2511_11354_amd import wig2
 
-    for kw in [dict(nx=6, nk=16), dict(nx=5, nk=32, precision="bf16x2"),
+    # (every torus plane size a context accepts, 16 ... 128, has the FFT route)
+    for kw in [dict(nx=5, nk=32, precision="bf16x2"),
                dict(nx=7, nk=32, periodic=False, sem_cells=4, x_min=-6.0, x_max=6.0, k_max=10 * np.pi / 3)]:
         nx, nk = kw.pop("nx"), kw.pop("nk")
         s = wig2.Solver(nx, nk, **kw)
